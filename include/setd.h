@@ -1,0 +1,189 @@
+/*
+ * setd.h - C ABI of the split-ETD3 library (libsetd.so) for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library advances stiff semilinear systems
+ *
+ *     u'(t) = K u(t) + g(u(t)),   K = A_d (+) ... (+) A_1   (Kronecker sum),
+ *
+ * with the third-order directionally split exponential Runge-Kutta method
+ * exprk3ds_real of Cassini, "Efficient third order tensor-oriented
+ * directional splitting for exponential integrators" (problem statement:
+ * Section 1, eqs. ODE and kronsum; method: eq. exprk3 with the splittings of
+ * Sections 2.1 and 2.3; pseudocode: Algorithms 1 and 2 of the appendix).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Tensors.  An order-d tensor V of size n_1 x ... x n_d is a flat array of
+ *   N = n_1 ... n_d elements with index i_1 fastest ("vec stacks by columns",
+ *   Section 2): element (i_1, ..., i_d) sits at
+ *   i_1 + n_1 (i_2 + n_2 (i_3 + ...)).
+ * Matrices.  Square n x n matrices are column-major: entry (i, j) at i + n j.
+ * Memory.  Every data pointer is DEVICE memory of the current HIP device unless
+ *   the argument says "host".  The caller owns all buffers passed in; the
+ *   library never frees them and never keeps them past the call (a context
+ *   copies what it needs).
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *   default stream).  Calls are asynchronous on that stream unless stated.
+ * Errors.  Every function returns SETD_OK (0) or a negative SETD_E* code.
+ *   Arguments are validated before anything is launched; on a validation
+ *   error nothing is written.  setd_last_error() gives a message for the
+ *   calling thread's last failure.  Nothing throws or aborts across the ABI.
+ */
+#ifndef SETD_H
+#define SETD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define SETD_OK            0
+#define SETD_EINVAL       -1   /* bad size, null pointer, aliasing, bad enum   */
+#define SETD_ENOMEM       -2   /* device allocation failed                     */
+#define SETD_EHIP         -3   /* a HIP runtime call or kernel launch failed   */
+#define SETD_ENONFINITE   -4   /* a non-finite value where one is not allowed  */
+#define SETD_EUNSUPPORTED -5   /* valid request outside what is implemented    */
+
+/* ---- arithmetic of the mu-mode products ---- */
+#define SETD_PREC_F64     0    /* FP64 operands, FP64 accumulate                */
+#define SETD_PREC_F32     1    /* FP32 operands and intermediates, FP32 accum.  */
+#define SETD_PREC_BF16X3  2    /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi on
+                                  MFMA with FP32 accumulate; FP32 intermediates */
+
+/* ---- reaction terms g (eq. twocompdisc: two components u, v) ---- */
+#define SETD_G_NONE         0  /* g = 0; nparams = 0                            */
+#define SETD_G_SCHNAKENBERG 1  /* params (gamma, a, b):
+                                  g1 = gamma (a - u + u^2 v), g2 = gamma (b - u^2 v)
+                                  (Section 3.1 model)                            */
+#define SETD_G_FHN          2  /* params (eps, a1, a0[, rho]), rho = 1 if absent:
+                                  g1 = rho (u - u^3 - v), g2 = rho eps (u - a1 v - a0)
+                                  (Section 3.2 model)                            */
+
+/* ---- stages of eq. exprk3 (argument scale c_s of the phi bank) ---- */
+#define SETD_STAGE_2  2        /* c = 1/3 */
+#define SETD_STAGE_3  3        /* c = 2/3 */
+#define SETD_STAGE_F  4        /* c = 1   */
+
+/*
+ * phi-functions of a small dense matrix (Section 1 definition
+ * phi_l(X) = sum_k X^k/(k+l)!; computed as in Section 2.4: rational Pade
+ * approximation with modified scaling and squaring, here entirely in FP64 on
+ * the GPU).
+ *
+ *   A     n x n column-major FP64 (device).
+ *   n     1 <= n <= 4096.
+ *   tau   scalar; the argument is X = tau * A.  Must be finite.
+ *   ell   0 <= ell <= 4.
+ *   out   (ell + 1) consecutive n x n column-major blocks (device):
+ *         phi_0(tau A), phi_1(tau A), ..., phi_ell(tau A).  Must not alias A.
+ *
+ * Synchronises `stream` once (the scaling exponent is chosen on the host from
+ * the norm computed on the device).  Returns SETD_ENONFINITE if A holds a
+ * non-finite value.
+ */
+int setd_phi_matrices(const double* A, int64_t n, double tau, int ell, double* out, void* stream);
+
+/*
+ * Tucker operator (Section 2, eq. krontomu):
+ *
+ *     W <- alpha * (V x_1 M_1 x_2 M_2 ... x_d M_d) + beta * W
+ *
+ *   V, W   N-element tensors (device), FP64, must not overlap.
+ *   d      1 <= d <= 8.
+ *   dims   host array of d sizes, 1 <= n_mu <= 4096.
+ *   M      host array of d device pointers; M[mu] is the n_mu x n_mu
+ *          column-major FP64 matrix applied along mode mu+1.  NULL means the
+ *          identity (that mode is skipped).
+ *   prec   SETD_PREC_F64, SETD_PREC_F32 or SETD_PREC_BF16X3 (arithmetic of the
+ *          mode products; V and W stay FP64).
+ *   ws     device workspace of at least setd_tucker_workspace_bytes(d, dims,
+ *          prec) bytes, or NULL to let the library use its own (grown on
+ *          demand, kept until setd_release_workspace or process exit).
+ *
+ * beta = 0 ignores the old contents of W (NaN included).
+ */
+int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims,
+                      const double* const* M, double alpha, double beta, int prec,
+                      void* ws, size_t ws_bytes, void* stream);
+size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec);
+int setd_release_workspace(void);
+
+/*
+ * Integration context: one grid, one set of matrices A_mu^(c) per component,
+ * one step size tau and one arithmetic.  Creating it builds the phi bank
+ * P_{i,s}^(l){mu} = phi_{l_i}(c_s tau alpha_{i,mu}^(l) A_mu) of Algorithm 1
+ * (d = 2, Table 1 real coefficients, 2 terms) or Algorithm 2 (d >= 3,
+ * Table 3, 3 terms), with the '+' coefficient set of Section 2.4, and every
+ * work buffer of the time step.
+ *
+ *   d       2 <= d <= 3.
+ *   dims    host array of d sizes, 2 <= n_mu <= 4096.
+ *   ncomp   number of components, 1 or 2 (the reactions need 2).
+ *   A       host array of ncomp*d device pointers: A[c*d + mu] is A_{mu+1}^(c),
+ *           n_mu x n_mu column-major FP64.  Copied; the caller may free them.
+ *   tau     step size > 0.
+ *   prec    arithmetic of the mu-mode products (SETD_PREC_*); u and the
+ *           stage accumulators are FP64 in every case.
+ *
+ * Synchronises `stream`.  Device memory held: about (23 N + bank) * 8 bytes
+ * per component in FP64.
+ */
+typedef struct setd_ctx setd_ctx;
+int setd_ctx_create(setd_ctx** ctx, int d, const int64_t* dims, int ncomp,
+                    const double* const* A, double tau, int prec, void* stream);
+int setd_ctx_destroy(setd_ctx* ctx);
+
+/*
+ * Split approximation of a phi-function action (eqs. split2d / splitnd3):
+ *
+ *     W <- beta * W + scale * S_l(c_s tau) V,
+ *     S_l(c tau) V = sum_i eta_i^(l) T(V, {P_{i,s}^(l){mu}})
+ *
+ *   comp    component whose matrices are used, 0 <= comp < ncomp.
+ *   ell     1 or 2 (stage SETD_STAGE_2 has ell = 1 only, as in the algorithms).
+ *   stage   SETD_STAGE_2, SETD_STAGE_3 or SETD_STAGE_F.
+ *   V, W    N-element FP64 tensors (device); must not overlap.
+ */
+int setd_split_phi_apply(setd_ctx* ctx, int comp, int ell, int stage, const double* V,
+                         double* W, double scale, double beta, void* stream);
+
+/*
+ * Time stepping: nsteps steps of eq. exprk3 with the split phi actions
+ * (the time loop of Algorithms 1 and 2), in place.
+ *
+ *   u        ncomp * N FP64 (device), component-major: u then v.
+ *   nsteps   >= 0.
+ *   tau      step size; if it differs from the context's, the phi bank is
+ *            rebuilt first (synchronising).
+ *   g_kind   SETD_G_*; params (host) and nparams as documented there.
+ *
+ * The diffusion coefficients live in the matrices A.  The K action uses a
+ * fused 3-point stencil when every A_mu^(c) is tridiagonal and dense mu-mode
+ * products otherwise.
+ */
+int setd_etd_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
+                  const double* params, int nparams, void* stream);
+
+/*
+ * Norms for error reporting (deterministic fixed-order reductions):
+ *   out[0] = ||x||_2, out[1] = ||x||_inf, and when y != NULL
+ *   out[2] = ||x - y||_2, out[3] = ||x - y||_inf   (out is host, 4 doubles).
+ * Synchronises `stream`.
+ */
+int setd_field_norms(const double* x, const double* y, int64_t n, double* out, void* stream);
+
+/* Message for the calling thread's last error ("" if none). */
+const char* setd_last_error(void);
+/* Waits for `stream` and reports an asynchronous HIP error as SETD_EHIP. */
+int setd_sync(void* stream);
+/* Library version string. */
+const char* setd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SETD_H */

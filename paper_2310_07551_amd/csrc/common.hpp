@@ -1,0 +1,115 @@
+// Internal helpers shared by the HIP sources of libsetd (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/setd.h"
+
+namespace setd {
+
+// ---- error reporting (thread-local message, status codes of setd.h) ----
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define SETD_CHECK_ARG(cond, ...)                 \
+  do {                                            \
+    if (!(cond)) {                                \
+      ::setd::set_error(__VA_ARGS__);             \
+      return SETD_EINVAL;                         \
+    }                                             \
+  } while (0)
+
+#define SETD_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::setd::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                        __FILE__, __LINE__);                                        \
+      return e_ == hipErrorOutOfMemory ? SETD_ENOMEM : SETD_EHIP;                   \
+    }                                                                               \
+  } while (0)
+
+#define SETD_TRY(expr)          \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != SETD_OK) return rc_; \
+  } while (0)
+
+// Launch-error check after a kernel launch.
+#define SETD_LAUNCHED()                                                              \
+  do {                                                                               \
+    hipError_t e_ = hipGetLastError();                                               \
+    if (e_ != hipSuccess) {                                                          \
+      ::setd::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                         \
+      return SETD_EHIP;                                                              \
+    }                                                                                \
+  } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// ---- device vector types ----
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+// Padded size of a packed matrix (rows and columns): multiple of 64 so that a
+// 64-row / 64-column wave tile never reads outside it.
+inline int packed_ld(int n) { return (int)round_up(n, 64); }
+
+// ---- mu-mode product job tables (see mode_f64.hip) ----
+constexpr int kMaxTerms = 3;
+constexpr int kMaxJobs = 20;
+
+// One output tensor Y[a, i, b] = base[a, i, b] + sum_t sum_p S_t[i, p] X_t[a, p, b]
+// over a (extent na, stride 1), i/p (extent n, stride na), b (extent nb,
+// stride na*n).  S_t is scale_t * P_t with P_t a packed matrix.
+struct ModeJob {
+  const void* X[kMaxTerms];
+  const void* P[kMaxTerms];   // packed matrix (layout depends on the kernel)
+  double scale[kMaxTerms];
+  void* Y;
+  const void* base;           // nullable
+  int64_t na, nb;
+  int n, ldp, nterms;
+  int tiles_a, tiles_i;       // tiles along a (or b for mode 1) and i
+  int64_t tile_begin;         // first logical tile of this job
+};
+
+struct ModeJobs {
+  ModeJob job[kMaxJobs];
+  int njobs;
+  int64_t total_tiles;
+};
+
+enum class DType : int { F64 = 0, F32 = 1 };
+
+// Mode-product launchers (implemented in mode_f64.hip / mode_lp.hip).
+// `jobs` is filled by the caller except for the tile fields, which the
+// launcher computes.  All jobs of one launch share regime (mode 1 or not).
+int launch_mode1_f64(ModeJobs& jobs, hipStream_t s);
+int launch_modeB_f64(ModeJobs& jobs, hipStream_t s);
+int launch_mode1_lp(ModeJobs& jobs, int prec, DType in, hipStream_t s);
+int launch_modeB_lp(ModeJobs& jobs, int prec, DType in, DType out, hipStream_t s);
+
+// Matrix packing (pointwise.hip).
+//   pack_rowmajor: PT[i*ldp + p] = scale*M[i + n p]   (mode-1 operand)
+//   pack_colmajor: P [i + ldp*p] = scale*M[i + n p]   (mode >= 2 operand)
+// zero outside n x n.
+int pack_matrix_f64(const double* M, int n, double scale, bool rowmajor, double* out, hipStream_t s);
+int pack_matrix_f32(const double* M, int n, double scale, bool rowmajor, float* out, hipStream_t s);
+int pack_matrix_bf16x2(const double* M, int n, double scale, bool rowmajor, void* out, hipStream_t s);
+size_t packed_bytes(int n, int prec);
+
+// Pointwise helpers (pointwise.hip).
+int launch_axpby(const double* x, double* y, int64_t n, double a, double b, hipStream_t s);  // y = a x + b y
+int launch_scale(double* y, int64_t n, double b, hipStream_t s);                              // y *= b (b == 0 -> 0)
+int launch_copy_convert(const double* x, void* y, int64_t n, DType out, hipStream_t s);
+
+}  // namespace setd

@@ -1,0 +1,376 @@
+// FP64 mu-mode products on the CDNA4 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// A mu-mode product S = T x_mu L (Section 2) applies L to every mu-fiber:
+// with a = (i_1..i_{mu-1}) flattened (stride 1), i = i_mu and b =
+// (i_{mu+1}..i_d) flattened,
+//
+//     Y[a, i, b] = sum_p L[i, p] X[a, p, b].
+//
+// Two kernels cover every mode:
+//   * mode 1 (no a index): Y = L X as a GEMM over the column-major unfolding
+//     X_(1) (n x N/n), no copy.  MFMA rows = i, columns = b, k = p.  The
+//     contraction index is the contiguous one, so each lane loads four
+//     consecutive p of one column (32 bytes) and uses them over four MFMA
+//     k-steps; the matrix is packed row-major (L[i, p] at i*ldp + p) to match.
+//   * modes >= 2: for each b, Y[:, :, b] = X[:, :, b] L^T with a contiguous.
+//     MFMA rows = a, columns = i, k = p.  Each lane loads TM consecutive a
+//     (one row of every row tile) and TN consecutive i of the column-major
+//     packed matrix, so every global access is a contiguous 16-32 byte run
+//     and a 16-lane group covers a full 128-byte line or more.
+//
+// Register tiling: a wave owns a (16 TM) x (16 TN) output tile held in
+// TM x TN MFMA accumulators; rows of the tile are interleaved (lane row m of
+// row-tile t is a0 + TM m + t) so the per-lane loads and the epilogue stores
+// are contiguous.  The next k-chunk is loaded into registers while the
+// current one feeds the MFMAs.
+//
+// Each launch runs a table of independent jobs (up to kMaxJobs outputs; each
+// may sum up to kMaxTerms inputs along the contraction, which is how the
+// terms of a split phi action are accumulated into one output), one wave per
+// workgroup, with the block index remapped so that each XCD gets a contiguous
+// range of tiles (neighbouring tiles share X or L in that XCD's L2).
+#include "common.hpp"
+
+#include <cstdlib>
+
+namespace setd {
+
+__device__ __forceinline__ int64_t remap_xcd(int64_t bid, int64_t per_xcd) {
+  return (bid & 7) * per_xcd + (bid >> 3);
+}
+
+__device__ __forceinline__ int find_job(const ModeJobs& J, int64_t t) {
+  int j = 0;
+  while (j + 1 < J.njobs && J.job[j + 1].tile_begin <= t) ++j;
+  return j;
+}
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// mode 1
+// ---------------------------------------------------------------------------
+template <int TM, int TN, bool VEC>
+__global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const ModeJob& jb = J.job[find_job(J, t)];
+  const int64_t lt = t - jb.tile_begin;
+  const int it = (int)(lt % jb.tiles_i);
+  const int64_t bt = lt / jb.tiles_i;
+
+  const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+  const int n = jb.n, ldp = jb.ldp;
+  const int64_t nb = jb.nb;
+  const int i0 = it * 16 * TM;
+  const int64_t b0 = bt * 16 * TN;
+  const double* __restrict__ X = (const double*)jb.X[0];
+  const double* __restrict__ PT = (const double*)jb.P[0];
+  const double sc = jb.scale[0];
+
+  const double* pa[TM];
+#pragma unroll
+  for (int m = 0; m < TM; ++m) pa[m] = PT + (int64_t)(i0 + TM * l + m) * ldp + 4 * g;
+  const double* pb[TN];
+  bool vb[TN];
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int64_t b = b0 + 16 * u + l;
+    vb[u] = b < nb;
+    pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + 4 * g;
+  }
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
+
+  d4 a[TM], bx[TN];
+  auto load = [&](int p0, d4* ar, d4* br) {
+#pragma unroll
+    for (int m = 0; m < TM; ++m) ar[m] = *(const d4*)(pa[m] + p0) * sc;
+    const bool full = VEC && (p0 + 16 <= n);
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      if (full) {
+        br[u] = vb[u] ? *(const d4*)(pb[u] + p0) : d4{0.0, 0.0, 0.0, 0.0};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] : 0.0;
+      }
+    }
+  };
+
+  load(0, a, bx);
+  for (int p0 = 0; p0 < n; p0 += 16) {
+    d4 an[TM], bn[TN];
+    const bool more = p0 + 16 < n;
+    if (more) load(p0 + 16, an, bn);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+#pragma unroll
+        for (int u = 0; u < TN; ++u) acc[m][u] = mfma(a[m][jj], bx[u][jj], acc[m][u]);
+    if (more) {
+#pragma unroll
+      for (int m = 0; m < TM; ++m) a[m] = an[m];
+#pragma unroll
+      for (int u = 0; u < TN; ++u) bx[u] = bn[u];
+    }
+  }
+
+  // Epilogue.  The FP64 16x16 accumulator holds tile row 4 r + g in register
+  // r of lane (g, l), column l; tile row q of row-tile m is output row
+  // i0 + TM q + m.  So lane (g, l) owns, for each r, the TM consecutive rows
+  // i0 + TM g + 4 TM r + (0..TM-1) of column b0 + 16 u + l.
+  double* __restrict__ Y = (double*)jb.Y;
+  const double* __restrict__ base = (const double*)jb.base;
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    if (!vb[u]) continue;
+    const int64_t col = (b0 + 16 * u + l) * (int64_t)n;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ir = i0 + TM * g + 4 * TM * r;
+      if (VEC && ir + TM <= n) {
+#pragma unroll
+        for (int m = 0; m < TM; m += 2) {
+          d2 w = d2{acc[m][u][r], acc[m + 1][u][r]};
+          if (base) w += *(const d2*)(base + col + ir + m);
+          *(d2*)(Y + col + ir + m) = w;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          if (ir + m < n) {
+            double w = acc[m][u][r];
+            if (base) w += base[col + ir + m];
+            Y[col + ir + m] = w;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// modes >= 2
+// ---------------------------------------------------------------------------
+template <int TM, int TN, bool VEC>
+__global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const ModeJob& jb = J.job[find_job(J, t)];
+  const int64_t lt = t - jb.tile_begin;
+  const int it = (int)(lt % jb.tiles_i);
+  const int64_t rest = lt / jb.tiles_i;
+  const int64_t at = rest % jb.tiles_a;
+  const int64_t b = rest / jb.tiles_a;
+
+  const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+  const int n = jb.n, ldp = jb.ldp, nterms = jb.nterms;
+  const int64_t na = jb.na;
+  const int64_t a0 = at * 16 * TM;
+  const int i0 = it * 16 * TN;
+  const int64_t arow = a0 + TM * l;                 // first of this lane's TM rows
+  const bool lane_full = arow + TM <= na;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t slab = na * (int64_t)n * b;
+  for (int term = 0; term < nterms; ++term) {
+    const double* __restrict__ xb = (const double*)jb.X[term] + slab + arow + na * g;
+    const double* __restrict__ pbp = (const double*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
+    const double sc = jb.scale[term];
+
+    auto load = [&](int p0, double* xr, double* pr) {
+      const bool vp = p0 + g < n;
+      const double* xs = xb + na * (int64_t)p0;
+      if (VEC && TM == 4 && lane_full && vp) {
+        const d4 v = *(const d4*)xs;
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = v[m];
+      } else if (VEC && TM == 2 && lane_full && vp) {
+        const d2 v = *(const d2*)xs;
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = v[m];
+      } else {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = (vp && arow + m < na) ? xs[m] : 0.0;
+      }
+      const double* ps = pbp + (int64_t)ldp * p0;
+      if (TN == 4) {
+        const d4 v = *(const d4*)ps * sc;
+#pragma unroll
+        for (int u = 0; u < TN; ++u) pr[u] = v[u];
+      } else if (TN == 2) {
+        const d2 v = *(const d2*)ps * sc;
+#pragma unroll
+        for (int u = 0; u < TN; ++u) pr[u] = v[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < TN; ++u) pr[u] = ps[u] * sc;
+      }
+    };
+
+    double xr[TM], pr[TN];
+    load(0, xr, pr);
+    for (int p0 = 0; p0 < n; p0 += 4) {
+      double xn[TM], pn[TN];
+      const bool more = p0 + 4 < n;
+      if (more) load(p0 + 4, xn, pn);
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+#pragma unroll
+        for (int u = 0; u < TN; ++u) acc[m][u] = mfma(xr[m], pr[u], acc[m][u]);
+      if (more) {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = xn[m];
+#pragma unroll
+        for (int u = 0; u < TN; ++u) pr[u] = pn[u];
+      }
+    }
+  }
+
+  // Epilogue (accumulator layout as in the mode-1 kernel): lane (g, l) owns,
+  // for each r, the TM consecutive a = a0 + TM g + 4 TM r + (0..TM-1) of
+  // column i = i0 + TN l + u.
+  double* __restrict__ Y = (double*)jb.Y;
+  const double* __restrict__ base = (const double*)jb.base;
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int i = i0 + TN * l + u;
+    if (i >= n) continue;
+    const int64_t off = slab + na * (int64_t)i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t ar = a0 + TM * g + 4 * TM * r;
+      if (VEC && ar + TM <= na) {
+#pragma unroll
+        for (int m = 0; m < TM; m += 2) {
+          d2 w = d2{acc[m][u][r], acc[m + 1][u][r]};
+          if (base) w += *(const d2*)(base + off + ar + m);
+          *(d2*)(Y + off + ar + m) = w;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          if (ar + m < na) {
+            double w = acc[m][u][r];
+            if (base) w += base[off + ar + m];
+            Y[off + ar + m] = w;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TileCfg {
+  int tm, tn;
+};
+
+TileCfg env_tile(const char* name, TileCfg def) {
+  const char* s = std::getenv(name);
+  if (!s) return def;
+  int a = 0, b = 0;
+  if (std::sscanf(s, "%dx%d", &a, &b) == 2 && (a == 2 || a == 4) && (b == 2 || b == 4)) return {a, b};
+  return def;
+}
+
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+int finish_tiles(ModeJobs& J, bool mode1, int TM, int TN) {
+  int64_t tot = 0;
+  for (int j = 0; j < J.njobs; ++j) {
+    ModeJob& jb = J.job[j];
+    if (mode1) {
+      jb.tiles_i = (int)ceil_div(jb.n, 16 * TM);
+      jb.tiles_a = (int)ceil_div(jb.nb, 16 * TN);     // tiles along b
+    } else {
+      jb.tiles_i = (int)ceil_div(jb.n, 16 * TN);
+      jb.tiles_a = (int)ceil_div(jb.na, 16 * TM);
+    }
+    jb.tile_begin = tot;
+    tot += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
+  }
+  J.total_tiles = tot;
+  return SETD_OK;
+}
+
+}  // namespace
+
+#define SETD_MODE1_CASE(TM_, TN_)                                                           \
+  if (cfg.tm == TM_ && cfg.tn == TN_) {                                                     \
+    if (vec)                                                                                \
+      hipLaunchKernelGGL((mode1_f64_kernel<TM_, TN_, true>), grid, dim3(64), 0, s, J, per); \
+    else                                                                                    \
+      hipLaunchKernelGGL((mode1_f64_kernel<TM_, TN_, false>), grid, dim3(64), 0, s, J, per);\
+    SETD_LAUNCHED();                                                                        \
+    return SETD_OK;                                                                         \
+  }
+
+#define SETD_MODEB_CASE(TM_, TN_)                                                           \
+  if (cfg.tm == TM_ && cfg.tn == TN_) {                                                     \
+    if (vec)                                                                                \
+      hipLaunchKernelGGL((modeB_f64_kernel<TM_, TN_, true>), grid, dim3(64), 0, s, J, per); \
+    else                                                                                    \
+      hipLaunchKernelGGL((modeB_f64_kernel<TM_, TN_, false>), grid, dim3(64), 0, s, J, per);\
+    SETD_LAUNCHED();                                                                        \
+    return SETD_OK;                                                                         \
+  }
+
+int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
+  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{4, 4});
+  finish_tiles(J, true, cfg.tm, cfg.tn);
+  if (J.total_tiles == 0) return SETD_OK;
+  bool vec = true;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    vec = vec && (jb.n % 4 == 0) && aligned(jb.X[0], 32) && aligned(jb.Y, 16) && aligned(jb.base, 16);
+  }
+  const int64_t per = ceil_div(J.total_tiles, 8);
+  const dim3 grid((unsigned)(per * 8));
+  SETD_MODE1_CASE(4, 4)
+  SETD_MODE1_CASE(4, 2)
+  SETD_MODE1_CASE(2, 4)
+  SETD_MODE1_CASE(2, 2)
+  set_error("unsupported mode-1 tile");
+  return SETD_EUNSUPPORTED;
+}
+
+int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
+  const TileCfg cfg = env_tile("SETD_TILE_MODEB", TileCfg{4, 4});
+  finish_tiles(J, false, cfg.tm, cfg.tn);
+  if (J.total_tiles == 0) return SETD_OK;
+  bool vec = true;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    vec = vec && (jb.na % 4 == 0) && aligned(jb.Y, 16) && aligned(jb.base, 16);
+    for (int t = 0; t < jb.nterms; ++t) vec = vec && aligned(jb.X[t], 32);
+  }
+  const int64_t per = ceil_div(J.total_tiles, 8);
+  const dim3 grid((unsigned)(per * 8));
+  SETD_MODEB_CASE(4, 4)
+  SETD_MODEB_CASE(4, 2)
+  SETD_MODEB_CASE(2, 4)
+  SETD_MODEB_CASE(2, 2)
+  set_error("unsupported mode-b tile");
+  return SETD_EUNSUPPORTED;
+}
+
+}  // namespace setd

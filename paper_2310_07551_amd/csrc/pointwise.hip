@@ -1,0 +1,310 @@
+// Pointwise and small helper kernels of the split-ETD3 step.
+//
+//  * packing of the small matrices into the layouts the mode kernels read;
+//  * G = g(U), F = K U + G (Algorithms 1-2, first line of the time loop) with
+//    K applied as a 3-point stencil per direction when every A_mu is
+//    tridiagonal (eq. kronsumv: K t = vec(sum_mu T x_mu A_mu), a tridiagonal
+//    A_mu touches the neighbours i_mu - 1, i_mu, i_mu + 1 only);
+//  * D = g(U_s) - G (stage differences d_ni of eq. ERK3);
+//  * deterministic norms (fixed-order two-pass reductions).
+// All of these are bound by HBM bandwidth: one thread per grid point,
+// contiguous along i_1, no reuse beyond the stencil neighbours.
+#include "common.hpp"
+#include "pointwise.hpp"
+
+namespace setd {
+
+// ---------------------------------------------------------------------------
+// packing
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void pack_kernel(const double* __restrict__ M, int n, int ldp, double scale, bool rowmajor,
+                            T* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ldp * ldp) return;
+  const int r = (int)(idx % ldp), c = (int)(idx / ldp);   // out index = r + ldp*c
+  // rowmajor: out[i*ldp + p] = M[i, p]  ->  r = p, c = i
+  // colmajor: out[i + ldp*p] = M[i, p]  ->  r = i, c = p
+  const int i = rowmajor ? c : r, p = rowmajor ? r : c;
+  double v = (i < n && p < n) ? scale * M[i + (int64_t)n * p] : 0.0;
+  out[idx] = (T)v;
+}
+
+// bf16 split: the packed buffer holds ldp*ldp hi values followed by ldp*ldp
+// lo values (round-to-nearest-even; x ~ hi + lo).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__global__ void pack_bf16x2_kernel(const double* __restrict__ M, int n, int ldp, double scale, bool rowmajor,
+                                   uint16_t* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)ldp * ldp;
+  if (idx >= tot) return;
+  const int r = (int)(idx % ldp), c = (int)(idx / ldp);
+  const int i = rowmajor ? c : r, p = rowmajor ? r : c;
+  const double v = (i < n && p < n) ? scale * M[i + (int64_t)n * p] : 0.0;
+  const float vf = (float)v;
+  const uint16_t hi = f32_to_bf16_rne(vf);
+  const uint16_t lo = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(hi)));
+  out[idx] = hi;
+  out[tot + idx] = lo;
+}
+
+size_t packed_bytes(int n, int prec) {
+  const size_t e = (size_t)packed_ld(n) * packed_ld(n);
+  if (prec == SETD_PREC_F64) return e * 8;
+  if (prec == SETD_PREC_F32) return e * 4;
+  return e * 4;   // two bf16 planes
+}
+
+int pack_matrix_f64(const double* M, int n, double scale, bool rowmajor, double* out, hipStream_t s) {
+  const int ldp = packed_ld(n);
+  const int64_t tot = (int64_t)ldp * ldp;
+  hipLaunchKernelGGL(pack_kernel<double>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, M, n, ldp, scale,
+                     rowmajor, out);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int pack_matrix_f32(const double* M, int n, double scale, bool rowmajor, float* out, hipStream_t s) {
+  const int ldp = packed_ld(n);
+  const int64_t tot = (int64_t)ldp * ldp;
+  hipLaunchKernelGGL(pack_kernel<float>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, M, n, ldp, scale,
+                     rowmajor, out);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int pack_matrix_bf16x2(const double* M, int n, double scale, bool rowmajor, void* out, hipStream_t s) {
+  const int ldp = packed_ld(n);
+  const int64_t tot = (int64_t)ldp * ldp;
+  hipLaunchKernelGGL(pack_bf16x2_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, M, n, ldp, scale,
+                     rowmajor, (uint16_t*)out);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// simple vector helpers
+// ---------------------------------------------------------------------------
+__global__ void axpby_kernel(const double* __restrict__ x, double* __restrict__ y, int64_t n, double a, double b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+__global__ void scale_kernel(double* __restrict__ y, int64_t n, double b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (b == 0.0) ? 0.0 : b * y[i];
+}
+
+template <typename T>
+__global__ void convert_kernel(const double* __restrict__ x, T* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)x[i];
+}
+
+int launch_axpby(const double* x, double* y, int64_t n, double a, double b, hipStream_t s) {
+  if (n == 0) return SETD_OK;
+  hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, y, n, a, b);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int launch_scale(double* y, int64_t n, double b, hipStream_t s) {
+  if (n == 0) return SETD_OK;
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, y, n, b);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int launch_copy_convert(const double* x, void* y, int64_t n, DType out, hipStream_t s) {
+  if (n == 0) return SETD_OK;
+  if (out == DType::F64)
+    hipLaunchKernelGGL(convert_kernel<double>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, (double*)y, n);
+  else
+    hipLaunchKernelGGL(convert_kernel<float>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, (float*)y, n);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reaction, G/F and stage kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void reaction(const GParams& P, double u, double v, double& g1, double& g2) {
+  if (P.kind == SETD_G_SCHNAKENBERG) {
+    const double u2v = u * u * v;
+    g1 = P.p[0] * (P.p[1] - u + u2v);
+    g2 = P.p[0] * (P.p[2] - u2v);
+  } else if (P.kind == SETD_G_FHN) {
+    const double rho = P.p[3];
+    g1 = rho * (u - u * u * u - v);
+    g2 = rho * P.p[0] * (u - P.p[1] * v - P.p[2]);
+  } else {
+    g1 = 0.0;
+    g2 = 0.0;
+  }
+}
+
+// One thread per grid point.  u holds ncomp fields of N points.  Writes
+// G_c = g_c(u) and F_c = (K_c u_c) + G_c for every component, and (when
+// out_f_lp != nullptr) also F in FP32 for the reduced-precision Tuckers.
+template <typename TF>
+__global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64_t N, int d, int n1, int n2,
+                                  int n3, StencilSet S, GParams gp, double* __restrict__ G, TF* __restrict__ F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  const int i1 = (int)(idx % n1);
+  const int64_t r = idx / n1;
+  const int i2 = (int)(r % n2);
+  const int i3 = (d == 3) ? (int)(r / n2) : 0;
+  const int idxs[3] = {i1, i2, i3};
+  const int ns[3] = {n1, n2, n3};
+  const int64_t strides[3] = {1, (int64_t)n1, (int64_t)n1 * n2};
+
+  double uc[2], g[2];
+  uc[0] = u[idx];
+  uc[1] = (ncomp > 1) ? u[N + idx] : 0.0;
+  reaction(gp, uc[0], uc[1], g[0], g[1]);
+  for (int c = 0; c < ncomp; ++c) {
+    const double* __restrict__ uu = u + (int64_t)c * N;
+    double k = 0.0;
+    for (int mu = 0; mu < d; ++mu) {
+      const int i = idxs[mu];
+      const int off = c * 3 + mu;
+      double t = S.di[off][i] * uc[c];
+      if (i > 0) t += S.lo[off][i] * uu[idx - strides[mu]];
+      if (i + 1 < ns[mu]) t += S.up[off][i] * uu[idx + strides[mu]];
+      k += t;
+    }
+    G[(int64_t)c * N + idx] = g[c];
+    F[(int64_t)c * N + idx] = (TF)(k + g[c]);
+  }
+}
+
+// G_c = g_c(u) only (the dense-K path adds the mode products afterwards).
+__global__ void g_kernel(const double* __restrict__ u, int ncomp, int64_t N, GParams gp, double* __restrict__ G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  double g[2];
+  reaction(gp, u[idx], ncomp > 1 ? u[N + idx] : 0.0, g[0], g[1]);
+  for (int c = 0; c < ncomp; ++c) G[(int64_t)c * N + idx] = g[c];
+}
+
+// D_c = g_c(Us) - G_c.
+template <typename TD>
+__global__ void stage_d_kernel(const double* __restrict__ Us, const double* __restrict__ G, int ncomp, int64_t N,
+                               GParams gp, TD* __restrict__ D) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  double g[2];
+  reaction(gp, Us[idx], ncomp > 1 ? Us[N + idx] : 0.0, g[0], g[1]);
+  for (int c = 0; c < ncomp; ++c) D[(int64_t)c * N + idx] = (TD)(g[c] - G[(int64_t)c * N + idx]);
+}
+
+int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* dims, const StencilSet& S,
+                      const GParams& gp, double* G, void* F, DType ftype, hipStream_t s) {
+  const int n3 = d == 3 ? dims[2] : 1;
+  const dim3 grid((unsigned)ceil_div(N, 256));
+  if (ftype == DType::F64)
+    hipLaunchKernelGGL(gf_stencil_kernel<double>, grid, dim3(256), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S,
+                       gp, G, (double*)F);
+  else
+    hipLaunchKernelGGL(gf_stencil_kernel<float>, grid, dim3(256), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S, gp,
+                       G, (float*)F);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int launch_g(const double* u, int ncomp, int64_t N, const GParams& gp, double* G, hipStream_t s) {
+  hipLaunchKernelGGL(g_kernel, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, u, ncomp, N, gp, G);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int launch_stage_d(const double* Us, const double* G, int ncomp, int64_t N, const GParams& gp, void* D,
+                   DType dtype, hipStream_t s) {
+  const dim3 grid((unsigned)ceil_div(N, 256));
+  if (dtype == DType::F64)
+    hipLaunchKernelGGL(stage_d_kernel<double>, grid, dim3(256), 0, s, Us, G, ncomp, N, gp, (double*)D);
+  else
+    hipLaunchKernelGGL(stage_d_kernel<float>, grid, dim3(256), 0, s, Us, G, ncomp, N, gp, (float*)D);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic norms
+// ---------------------------------------------------------------------------
+constexpr int kNormBlocks = 512;
+constexpr int kNormThreads = 256;
+
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
+}
+
+__global__ void norm_pass1(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+                           double* __restrict__ part) {
+  __shared__ double s[4][kNormThreads];
+  const int64_t chunk = ceil_div_dev(n, (int64_t)gridDim.x);
+  const int64_t beg = chunk * blockIdx.x;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double ss = 0.0, mx = 0.0, dss = 0.0, dmx = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const double v = x[i];
+    ss += v * v;
+    mx = nanmax(mx, fabs(v));
+    if (y) {
+      const double e = v - y[i];
+      dss += e * e;
+      dmx = nanmax(dmx, fabs(e));
+    }
+  }
+  s[0][threadIdx.x] = ss;
+  s[1][threadIdx.x] = mx;
+  s[2][threadIdx.x] = dss;
+  s[3][threadIdx.x] = dmx;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + w];
+      s[1][threadIdx.x] = nanmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+      s[2][threadIdx.x] += s[2][threadIdx.x + w];
+      s[3][threadIdx.x] = nanmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = s[k][0];
+}
+
+__global__ void norm_pass2(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double ss = 0, mx = 0, dss = 0, dmx = 0;
+  for (int b = 0; b < nblk; ++b) {
+    ss += part[4 * b];
+    mx = nanmax(mx, part[4 * b + 1]);
+    dss += part[4 * b + 2];
+    dmx = nanmax(dmx, part[4 * b + 3]);
+  }
+  out[0] = sqrt(ss);
+  out[1] = mx;
+  out[2] = sqrt(dss);
+  out[3] = dmx;
+}
+
+size_t norm_workspace_bytes() { return (size_t)(4 * kNormBlocks + 4) * sizeof(double); }
+
+int launch_norms(const double* x, const double* y, int64_t n, double* ws, hipStream_t s) {
+  hipLaunchKernelGGL(norm_pass1, dim3(kNormBlocks), dim3(kNormThreads), 0, s, x, y, n, ws);
+  SETD_LAUNCHED();
+  hipLaunchKernelGGL(norm_pass2, dim3(1), dim3(64), 0, s, ws, kNormBlocks, ws + 4 * kNormBlocks);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+}  // namespace setd

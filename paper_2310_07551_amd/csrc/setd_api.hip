@@ -1,0 +1,768 @@
+// C ABI of libsetd: argument checking, the phi bank, and the orchestration of
+// the split-ETD3 step (the time loop of Algorithms 1 and 2) on top of the
+// mode-product and pointwise kernels.
+//
+// One step, for both components at once (g couples them pointwise):
+//   1. G = g(U), F = K U + G                                 (pointwise/stencil)
+//   2. the phi_1 Tuckers on F for the three stages (3 x nterms per
+//      component) in three grouped launches (one per mode); the last mode
+//      sums the terms of each split phi action along the contraction and adds
+//      U:  U2 = U + tau/3 S_1(tau/3) F,  U3 = U + 2tau/3 S_1(2tau/3) F,
+//          W  = U + tau S_1(tau) F
+//   3. D = g(U2) - G
+//   4. U3 += 4tau/3 S_2(2tau/3) D
+//   5. D = g(U3) - G
+//   6. U  = W + 3tau/2 S_2(tau) D
+// Every split phi action S_l(c tau) V = sum_i eta_i T(V, {P_{i,s}^(l){mu}})
+// (eqs. split2d / splitnd3) costs nterms Tuckers of d mu-mode products.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "coeffs.hpp"
+#include "common.hpp"
+#include "pointwise.hpp"
+
+namespace setd {
+
+static thread_local char g_err[1024];
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+
+namespace {
+
+// Bank entries of Algorithms 1-2: (stage, ell) pairs.
+const int kBankStage[5] = {SETD_STAGE_2, SETD_STAGE_3, SETD_STAGE_3, SETD_STAGE_F, SETD_STAGE_F};
+const int kBankEll[5] = {1, 1, 2, 1, 2};
+
+int bank_index(int stage, int ell) {
+  for (int e = 0; e < 5; ++e)
+    if (kBankStage[e] == stage && kBankEll[e] == ell) return e;
+  return -1;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int alloc(size_t b) {
+    release();
+    if (b == 0) return SETD_OK;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      set_error("hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+      return SETD_ENOMEM;
+    }
+    bytes = b;
+    return SETD_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+}  // namespace
+}  // namespace setd
+
+using namespace setd;
+
+struct setd_ctx {
+  int d = 0, ncomp = 0, prec = SETD_PREC_F64;
+  int dims[3] = {1, 1, 1};
+  int64_t N = 0;
+  double tau = 0.0;
+  std::vector<double> Ah[2][3];
+  bool tridiag = false;
+  StencilSet st{};
+  Splitting sp[3];
+  int nterms = 0;
+  void* bank[2][5][3][3] = {};   // [comp][entry][term][mu] packed FP64 matrix
+  void* Apk[2][3] = {};          // packed A for the dense K path
+  double *G = nullptr, *F = nullptr, *U2 = nullptr, *U3 = nullptr, *W = nullptr, *D = nullptr;
+  double* Y1[2][9] = {};
+  double* Y2[2][9] = {};
+  double* norm_ws = nullptr;
+  DevBuf A_mem, stencil_mem, bank_mem, work_mem;
+};
+
+namespace {
+
+ModeJob mk_job(const void* X, const void* P, double scale, void* Y, const void* base, int64_t na, int n,
+               int64_t nb) {
+  ModeJob j{};
+  j.X[0] = X;
+  j.P[0] = P;
+  j.scale[0] = scale;
+  j.nterms = 1;
+  j.Y = Y;
+  j.base = base;
+  j.na = na;
+  j.nb = nb;
+  j.n = n;
+  j.ldp = packed_ld(n);
+  return j;
+}
+
+// One Tucker-summed output: Y = base + sum_t scale_t T(X_t, {P_t[mu]}).
+struct TuckerTerm {
+  const double* X;
+  void* const* P;       // d packed matrices (mode 1 row-major, others column-major)
+  double scale;
+  double* Y1;
+  double* Y2;
+};
+struct TuckerOut {
+  double* Y;
+  const double* base;
+  int nterms;
+  TuckerTerm term[kMaxTerms];
+};
+
+int flush(ModeJobs& J, bool mode1, hipStream_t s) {
+  if (J.njobs == 0) return SETD_OK;
+  int rc = mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
+  J.njobs = 0;
+  return rc;
+}
+
+int push(ModeJobs& J, const ModeJob& jb, bool mode1, hipStream_t s) {
+  if (J.njobs == kMaxJobs) SETD_TRY(flush(J, mode1, s));
+  J.job[J.njobs++] = jb;
+  return SETD_OK;
+}
+
+// Runs all outputs of a group: d grouped launches (or more if a launch
+// would exceed kMaxJobs).  dims has d >= 2 entries.
+int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, hipStream_t s) {
+  int64_t N = 1;
+  for (int mu = 0; mu < d; ++mu) N *= dims[mu];
+  ModeJobs J;
+  J.njobs = 0;
+  // mode 1 -> Y1
+  for (int o = 0; o < nouts; ++o)
+    for (int t = 0; t < outs[o].nterms; ++t) {
+      const TuckerTerm& tm = outs[o].term[t];
+      SETD_TRY(push(J, mk_job(tm.X, tm.P[0], 1.0, tm.Y1, nullptr, 1, dims[0], N / dims[0]), true, s));
+    }
+  SETD_TRY(flush(J, true, s));
+  // inner modes, ping-pong Y1 <-> Y2
+  int64_t na = dims[0];
+  for (int mu = 1; mu < d - 1; ++mu) {
+    const int64_t nb = N / (na * dims[mu]);
+    for (int o = 0; o < nouts; ++o)
+      for (int t = 0; t < outs[o].nterms; ++t) {
+        const TuckerTerm& tm = outs[o].term[t];
+        const double* src = (mu % 2 == 1) ? tm.Y1 : tm.Y2;
+        double* dst = (mu % 2 == 1) ? tm.Y2 : tm.Y1;
+        SETD_TRY(push(J, mk_job(src, tm.P[mu], 1.0, dst, nullptr, na, dims[mu], nb), false, s));
+      }
+    SETD_TRY(flush(J, false, s));
+    na *= dims[mu];
+  }
+  // last mode: terms summed along the contraction, base added
+  const int mu = d - 1;
+  for (int o = 0; o < nouts; ++o) {
+    ModeJob jb{};
+    jb.nterms = outs[o].nterms;
+    for (int t = 0; t < outs[o].nterms; ++t) {
+      const TuckerTerm& tm = outs[o].term[t];
+      jb.X[t] = (mu % 2 == 1) ? tm.Y1 : tm.Y2;
+      jb.P[t] = tm.P[mu];
+      jb.scale[t] = tm.scale;
+    }
+    jb.Y = outs[o].Y;
+    jb.base = outs[o].base;
+    jb.na = na;
+    jb.nb = 1;
+    jb.n = dims[mu];
+    jb.ldp = packed_ld(dims[mu]);
+    SETD_TRY(push(J, jb, false, s));
+  }
+  return flush(J, false, s);
+}
+
+bool is_tridiagonal(const std::vector<double>& A, int n) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i)
+      if ((i - j > 1 || j - i > 1) && A[i + (size_t)n * j] != 0.0) return false;
+  return true;
+}
+
+int build_bank(setd_ctx* c, hipStream_t s) {
+  const int d = c->d;
+  // device copies of A (for phi and the dense K path)
+  size_t abytes = 0;
+  for (int cc = 0; cc < c->ncomp; ++cc)
+    for (int mu = 0; mu < d; ++mu) abytes += (size_t)c->dims[mu] * c->dims[mu] * sizeof(double);
+  if (c->A_mem.p == nullptr) {
+    SETD_TRY(c->A_mem.alloc(abytes));
+    char* q = (char*)c->A_mem.p;
+    for (int cc = 0; cc < c->ncomp; ++cc)
+      for (int mu = 0; mu < d; ++mu) {
+        const size_t b = (size_t)c->dims[mu] * c->dims[mu] * sizeof(double);
+        SETD_HIP(hipMemcpyAsync(q, c->Ah[cc][mu].data(), b, hipMemcpyHostToDevice, s));
+        q += b;
+      }
+  }
+  auto Adev = [&](int cc, int mu) {
+    char* q = (char*)c->A_mem.p;
+    for (int k = 0; k < cc * d + mu; ++k) {
+      const int m = c->dims[k % d];
+      q += (size_t)m * m * sizeof(double);
+    }
+    return (const double*)q;
+  };
+
+  // packed bank + packed A
+  size_t bbytes = 0;
+  for (int cc = 0; cc < c->ncomp; ++cc)
+    for (int mu = 0; mu < d; ++mu) bbytes += (5 * c->nterms + 1) * packed_bytes(c->dims[mu], SETD_PREC_F64);
+  SETD_TRY(c->bank_mem.alloc(bbytes));
+  {
+    char* q = (char*)c->bank_mem.p;
+    for (int cc = 0; cc < c->ncomp; ++cc)
+      for (int mu = 0; mu < d; ++mu) {
+        const size_t pb = packed_bytes(c->dims[mu], SETD_PREC_F64);
+        for (int e = 0; e < 5; ++e)
+          for (int t = 0; t < c->nterms; ++t) {
+            c->bank[cc][e][t][mu] = q;
+            q += pb;
+          }
+        c->Apk[cc][mu] = q;
+        q += pb;
+      }
+  }
+
+  for (int cc = 0; cc < c->ncomp; ++cc) {
+    // raw phi_0..phi_2 of each direction's scalars; a later direction with
+    // the same matrix and the same scalars reuses an earlier one's
+    DevBuf raw[3];
+    std::vector<double> scal[3];
+    std::vector<int> which[3];   // e * 3 + t
+    int rep[3];
+    for (int mu = 0; mu < d; ++mu) {
+      for (int e = 0; e < 5; ++e) {
+        const Splitting& S = c->sp[kBankEll[e]];
+        for (int t = 0; t < S.nterms; ++t) {
+          scal[mu].push_back(stage_scale(kBankStage[e]) * c->tau * S.alpha[t][mu]);
+          which[mu].push_back(e * 3 + t);
+        }
+      }
+      rep[mu] = mu;
+      for (int nu = 0; nu < mu; ++nu)
+        if (rep[nu] == nu && c->dims[nu] == c->dims[mu] && c->Ah[cc][nu] == c->Ah[cc][mu] &&
+            scal[nu] == scal[mu]) {
+          rep[mu] = nu;
+          break;
+        }
+      const int n = c->dims[mu];
+      const int E = (int)scal[mu].size();
+      const size_t nn = (size_t)n * n;
+      if (rep[mu] == mu) {
+        SETD_TRY(raw[mu].alloc((size_t)E * 3 * nn * sizeof(double)));
+        std::vector<double*> outs(E * 3);
+        for (int k = 0; k < E * 3; ++k) outs[k] = (double*)raw[mu].p + (size_t)k * nn;
+        SETD_TRY(phi_batch(Adev(cc, mu), n, scal[mu].data(), E, 2, outs.data(), s));
+      }
+      const double* src = (const double*)raw[rep[mu]].p;
+      const bool rowmajor = (mu == 0);
+      for (int k = 0; k < E; ++k) {
+        const int e = which[mu][k] / 3, t = which[mu][k] % 3;
+        const int li = c->sp[kBankEll[e]].ell_i[t];
+        SETD_TRY(pack_matrix_f64(src + ((size_t)k * 3 + li) * nn, n, 1.0, rowmajor, (double*)c->bank[cc][e][t][mu],
+                                 s));
+      }
+      SETD_TRY(pack_matrix_f64(Adev(cc, mu), n, 1.0, rowmajor, (double*)c->Apk[cc][mu], s));
+    }
+    SETD_HIP(hipStreamSynchronize(s));   // raw buffers are released at scope exit
+  }
+  SETD_HIP(hipStreamSynchronize(s));
+  return SETD_OK;
+}
+
+int make_gparams(int g_kind, const double* params, int nparams, int ncomp, GParams& gp) {
+  gp.kind = g_kind;
+  gp.p[0] = gp.p[1] = gp.p[2] = 0.0;
+  gp.p[3] = 1.0;
+  if (g_kind == SETD_G_NONE) {
+    SETD_CHECK_ARG(nparams == 0 || params != nullptr, "params is NULL");
+    return SETD_OK;
+  }
+  SETD_CHECK_ARG(ncomp == 2, "reaction kind %d needs two components", g_kind);
+  SETD_CHECK_ARG(params != nullptr, "params is NULL");
+  if (g_kind == SETD_G_SCHNAKENBERG) {
+    SETD_CHECK_ARG(nparams == 3, "Schnakenberg takes 3 parameters (gamma, a, b)");
+  } else if (g_kind == SETD_G_FHN) {
+    SETD_CHECK_ARG(nparams == 3 || nparams == 4, "FitzHugh-Nagumo takes 3 or 4 parameters (eps, a1, a0[, rho])");
+  } else {
+    SETD_CHECK_ARG(false, "unknown reaction kind %d", g_kind);
+  }
+  for (int k = 0; k < nparams; ++k) {
+    if (!std::isfinite(params[k])) {
+      set_error("reaction parameter %d is not finite", k);
+      return SETD_ENONFINITE;
+    }
+    gp.p[k] = params[k];
+  }
+  return SETD_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+// Split phi action outputs for the F group: stage s, ell = 1.
+int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+  const int d = c->d, nc = c->ncomp, T = c->nterms;
+  const int64_t N = c->N;
+  const double tau = c->tau;
+  // 1. G, F
+  if (c->tridiag) {
+    SETD_TRY(launch_gf_stencil(u, nc, N, d, c->dims, c->st, gp, c->G, c->F, DType::F64, s));
+  } else {
+    SETD_TRY(launch_g(u, nc, N, gp, c->G, s));
+    for (int cc = 0; cc < nc; ++cc) {
+      double* Fc = c->F + cc * N;
+      const double* uc = u + cc * N;
+      ModeJobs J;
+      J.njobs = 1;
+      J.job[0] = mk_job(uc, c->Apk[cc][0], 1.0, Fc, c->G + cc * N, 1, c->dims[0], N / c->dims[0]);
+      SETD_TRY(launch_mode1_f64(J, s));
+      int64_t na = c->dims[0];
+      for (int mu = 1; mu < d; ++mu) {
+        J.njobs = 1;
+        J.job[0] = mk_job(uc, c->Apk[cc][mu], 1.0, Fc, Fc, na, c->dims[mu], N / (na * c->dims[mu]));
+        SETD_TRY(launch_modeB_f64(J, s));
+        na *= c->dims[mu];
+      }
+    }
+  }
+  const int e21 = bank_index(SETD_STAGE_2, 1), e31 = bank_index(SETD_STAGE_3, 1), e32 = bank_index(SETD_STAGE_3, 2),
+            ef1 = bank_index(SETD_STAGE_F, 1), ef2 = bank_index(SETD_STAGE_F, 2);
+  const Splitting& S1 = c->sp[1];
+  const Splitting& S2 = c->sp[2];
+  // 2. phi_1 actions on F for the three stages
+  {
+    TuckerOut outs[6];
+    int no = 0;
+    for (int cc = 0; cc < nc; ++cc) {
+      const struct {
+        int e;
+        double mult;
+        double* Y;
+      } tg[3] = {{e21, tau / 3.0, c->U2 + cc * N}, {e31, 2.0 * tau / 3.0, c->U3 + cc * N}, {ef1, tau, c->W + cc * N}};
+      for (int k = 0; k < 3; ++k) {
+        TuckerOut& o = outs[no++];
+        o.Y = tg[k].Y;
+        o.base = u + cc * N;
+        o.nterms = T;
+        for (int t = 0; t < T; ++t)
+          o.term[t] = {c->F + cc * N, c->bank[cc][tg[k].e][t], tg[k].mult * S1.eta[t], c->Y1[cc][k * T + t],
+                       c->Y2[cc][k * T + t]};
+      }
+    }
+    SETD_TRY(run_tucker_group(d, c->dims, outs, no, s));
+  }
+  // 3. D = g(U2) - G
+  SETD_TRY(launch_stage_d(c->U2, c->G, nc, N, gp, c->D, DType::F64, s));
+  // 4. U3 += 4tau/3 S_2(2tau/3) D
+  {
+    TuckerOut outs[2];
+    for (int cc = 0; cc < nc; ++cc) {
+      TuckerOut& o = outs[cc];
+      o.Y = c->U3 + cc * N;
+      o.base = c->U3 + cc * N;
+      o.nterms = T;
+      for (int t = 0; t < T; ++t)
+        o.term[t] = {c->D + cc * N, c->bank[cc][e32][t], 4.0 * tau / 3.0 * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
+    }
+    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, s));
+  }
+  // 5. D = g(U3) - G
+  SETD_TRY(launch_stage_d(c->U3, c->G, nc, N, gp, c->D, DType::F64, s));
+  // 6. U = W + 3tau/2 S_2(tau) D
+  {
+    TuckerOut outs[2];
+    for (int cc = 0; cc < nc; ++cc) {
+      TuckerOut& o = outs[cc];
+      o.Y = u + cc * N;
+      o.base = c->W + cc * N;
+      o.nterms = T;
+      for (int t = 0; t < T; ++t)
+        o.term[t] = {c->D + cc * N, c->bank[cc][ef2][t], 1.5 * tau * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
+    }
+    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, s));
+  }
+  return SETD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* setd_last_error(void) { return g_err; }
+
+const char* setd_version(void) { return "setd 0.1 (gfx950, FP64 MFMA mode products)"; }
+
+int setd_sync(void* stream) {
+  clear_error();
+  SETD_HIP(hipStreamSynchronize((hipStream_t)stream));
+  SETD_HIP(hipGetLastError());
+  return SETD_OK;
+}
+
+int setd_release_workspace(void) {
+  clear_error();
+  int dev = 0;
+  SETD_HIP(hipGetDevice(&dev));
+  hipMemPool_t pool;
+  SETD_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  SETD_HIP(hipMemPoolTrimTo(pool, 0));
+  return SETD_OK;
+}
+
+int setd_phi_matrices(const double* A, int64_t n, double tau, int ell, double* out, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(A != nullptr && out != nullptr, "A and out must be non-NULL");
+  SETD_CHECK_ARG(n >= 1 && n <= 4096, "n = %lld outside 1..4096", (long long)n);
+  SETD_CHECK_ARG(ell >= 0 && ell <= 4, "ell = %d outside 0..4", ell);
+  SETD_CHECK_ARG(!overlap(A, (size_t)n * n * 8, out, (size_t)(ell + 1) * n * n * 8), "out overlaps A");
+  if (!std::isfinite(tau)) {
+    set_error("tau is not finite");
+    return SETD_ENONFINITE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double*> outs(ell + 1);
+  for (int k = 0; k <= ell; ++k) outs[k] = out + (size_t)k * n * n;
+  return phi_batch(A, (int)n, &tau, 1, ell, outs.data(), s);
+}
+
+size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec) {
+  if (d < 1 || d > 8 || dims == nullptr) return 0;
+  int64_t N = 1;
+  size_t pk = 0;
+  for (int mu = 0; mu < d; ++mu) {
+    if (dims[mu] < 1 || dims[mu] > 4096) return 0;
+    N *= dims[mu];
+    pk += round_up(packed_bytes((int)dims[mu], SETD_PREC_F64), 256);
+  }
+  (void)prec;
+  return pk + 2 * round_up(N * (int64_t)sizeof(double), 256) + 256;
+}
+
+int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, const double* const* M, double alpha,
+                      double beta, int prec, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(d >= 1 && d <= 8, "d = %d outside 1..8", d);
+  SETD_CHECK_ARG(dims != nullptr && M != nullptr, "dims and M must be non-NULL");
+  SETD_CHECK_ARG(V != nullptr && W != nullptr, "V and W must be non-NULL");
+  int64_t N = 1;
+  for (int mu = 0; mu < d; ++mu) {
+    SETD_CHECK_ARG(dims[mu] >= 1 && dims[mu] <= 4096, "dims[%d] = %lld outside 1..4096", mu, (long long)dims[mu]);
+    N *= dims[mu];
+  }
+  SETD_CHECK_ARG(!overlap(V, N * 8, W, N * 8), "V and W overlap");
+  SETD_CHECK_ARG(prec == SETD_PREC_F64, "only SETD_PREC_F64 is implemented for setd_tucker_apply");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) {
+    set_error("alpha/beta not finite");
+    return SETD_ENONFINITE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = setd_tucker_workspace_bytes(d, dims, prec);
+  SETD_CHECK_ARG(ws == nullptr || ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+
+  int modes[8], nm = 0;
+  for (int mu = 0; mu < d; ++mu)
+    if (M[mu] != nullptr) modes[nm++] = mu;
+  // beta handling: base = W when beta == 1, none when beta == 0, else scale W first
+  const double* base = nullptr;
+  if (beta != 0.0) {
+    if (beta != 1.0) SETD_TRY(launch_scale(W, N, beta, s));
+    base = W;
+  }
+  if (nm == 0) {
+    return launch_axpby(V, W, N, alpha, beta == 0.0 ? 0.0 : 1.0, s);
+  }
+  void* wsp = ws;
+  bool own = false;
+  if (wsp == nullptr) {
+    SETD_HIP(hipMallocAsync(&wsp, need, s));
+    own = true;
+  }
+  char* q = (char*)round_up((int64_t)(uintptr_t)wsp, 256);
+  double* buf[2] = {(double*)q, (double*)(q + round_up(N * 8, 256))};
+  q += 2 * round_up(N * 8, 256);
+  void* P[8] = {};
+  int rc = SETD_OK;
+  for (int k = 0; k < nm && rc == SETD_OK; ++k) {
+    const int mu = modes[k];
+    P[mu] = q;
+    q += round_up(packed_bytes((int)dims[mu], SETD_PREC_F64), 256);
+    const bool last = (k == nm - 1);
+    rc = pack_matrix_f64(M[mu], (int)dims[mu], last ? alpha : 1.0, mu == 0, (double*)P[mu], s);
+  }
+  const double* src = V;
+  for (int k = 0; k < nm && rc == SETD_OK; ++k) {
+    const int mu = modes[k];
+    const bool last = (k == nm - 1);
+    double* dst = last ? W : buf[k & 1];
+    int64_t na = 1, nb = 1;
+    for (int nu = 0; nu < mu; ++nu) na *= dims[nu];
+    for (int nu = mu + 1; nu < d; ++nu) nb *= dims[nu];
+    ModeJobs J;
+    J.njobs = 1;
+    J.job[0] = mk_job(src, P[mu], 1.0, dst, last ? base : nullptr, na, (int)dims[mu], nb);
+    rc = (mu == 0) ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
+    src = dst;
+  }
+  if (own) {
+    hipError_t e = hipFreeAsync(wsp, s);
+    if (rc == SETD_OK && e != hipSuccess) {
+      set_error("hipFreeAsync failed: %s", hipGetErrorString(e));
+      rc = SETD_EHIP;
+    }
+  }
+  return rc;
+}
+
+int setd_ctx_create(setd_ctx** out, int d, const int64_t* dims, int ncomp, const double* const* A, double tau,
+                    int prec, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(out != nullptr, "ctx out-pointer is NULL");
+  *out = nullptr;
+  SETD_CHECK_ARG(d == 2 || d == 3, "d = %d: the split integrator supports d = 2 and d = 3", d);
+  SETD_CHECK_ARG(dims != nullptr && A != nullptr, "dims and A must be non-NULL");
+  SETD_CHECK_ARG(ncomp == 1 || ncomp == 2, "ncomp = %d outside 1..2", ncomp);
+  SETD_CHECK_ARG(tau > 0.0, "tau must be positive");
+  if (!std::isfinite(tau)) {
+    set_error("tau is not finite");
+    return SETD_ENONFINITE;
+  }
+  SETD_CHECK_ARG(prec == SETD_PREC_F64 || prec == SETD_PREC_F32 || prec == SETD_PREC_BF16X3, "bad prec %d", prec);
+  if (prec != SETD_PREC_F64) {
+    set_error("reduced-precision contexts are not built in this library version");
+    return SETD_EUNSUPPORTED;
+  }
+  for (int mu = 0; mu < d; ++mu)
+    SETD_CHECK_ARG(dims[mu] >= 2 && dims[mu] <= 1024, "dims[%d] = %lld outside 2..1024", mu, (long long)dims[mu]);
+  for (int k = 0; k < ncomp * d; ++k) SETD_CHECK_ARG(A[k] != nullptr, "A[%d] is NULL", k);
+  hipStream_t s = (hipStream_t)stream;
+
+  setd_ctx* c = new (std::nothrow) setd_ctx();
+  if (!c) {
+    set_error("out of host memory");
+    return SETD_ENOMEM;
+  }
+  c->d = d;
+  c->ncomp = ncomp;
+  c->prec = prec;
+  c->tau = tau;
+  c->N = 1;
+  for (int mu = 0; mu < d; ++mu) {
+    c->dims[mu] = (int)dims[mu];
+    c->N *= dims[mu];
+  }
+  c->sp[1] = splitting(1, d);
+  c->sp[2] = splitting(2, d);
+  c->nterms = c->sp[1].nterms;
+
+  int rc = SETD_OK;
+  auto fail = [&](int code) {
+    delete c;
+    return code;
+  };
+  // host copies of A; tridiagonal check; finiteness
+  c->tridiag = true;
+  for (int cc = 0; cc < ncomp; ++cc)
+    for (int mu = 0; mu < d; ++mu) {
+      const int n = c->dims[mu];
+      c->Ah[cc][mu].resize((size_t)n * n);
+      hipError_t e = hipMemcpy(c->Ah[cc][mu].data(), A[cc * d + mu], (size_t)n * n * 8, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        set_error("copying A[%d] failed: %s", cc * d + mu, hipGetErrorString(e));
+        return fail(SETD_EHIP);
+      }
+      for (double v : c->Ah[cc][mu])
+        if (!std::isfinite(v)) {
+          set_error("A[%d] has non-finite entries", cc * d + mu);
+          return fail(SETD_ENONFINITE);
+        }
+      c->tridiag = c->tridiag && is_tridiagonal(c->Ah[cc][mu], n);
+    }
+  // stencil coefficients
+  if (c->tridiag) {
+    size_t tot = 0;
+    for (int cc = 0; cc < ncomp; ++cc)
+      for (int mu = 0; mu < d; ++mu) tot += 3 * (size_t)c->dims[mu];
+    std::vector<double> h(tot);
+    size_t o = 0;
+    std::vector<size_t> offs;
+    for (int cc = 0; cc < ncomp; ++cc)
+      for (int mu = 0; mu < d; ++mu) {
+        const int n = c->dims[mu];
+        const std::vector<double>& M = c->Ah[cc][mu];
+        offs.push_back(o);
+        for (int i = 0; i < n; ++i) {
+          h[o + i] = i > 0 ? M[i + (size_t)n * (i - 1)] : 0.0;
+          h[o + n + i] = M[i + (size_t)n * i];
+          h[o + 2 * n + i] = i + 1 < n ? M[i + (size_t)n * (i + 1)] : 0.0;
+        }
+        o += 3 * n;
+      }
+    if ((rc = c->stencil_mem.alloc(tot * 8)) != SETD_OK) return fail(rc);
+    hipError_t e = hipMemcpy(c->stencil_mem.p, h.data(), tot * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      set_error("stencil upload failed: %s", hipGetErrorString(e));
+      return fail(SETD_EHIP);
+    }
+    int k = 0;
+    for (int cc = 0; cc < ncomp; ++cc)
+      for (int mu = 0; mu < d; ++mu, ++k) {
+        const double* base = (const double*)c->stencil_mem.p + offs[k];
+        const int n = c->dims[mu];
+        c->st.lo[cc * 3 + mu] = base;
+        c->st.di[cc * 3 + mu] = base + n;
+        c->st.up[cc * 3 + mu] = base + 2 * n;
+      }
+  }
+  // work buffers: G F U2 U3 W D (ncomp*N each) + Y1/Y2 (3*nterms per component)
+  {
+    const int T = c->nterms;
+    const int ny = 3 * T;
+    const int64_t fields = 6 * (int64_t)ncomp + (int64_t)ncomp * ny * (d == 3 ? 2 : 1);
+    const size_t fb = round_up(c->N * 8, 256);
+    if ((rc = c->work_mem.alloc(fields * fb + norm_workspace_bytes() + 256)) != SETD_OK) return fail(rc);
+    char* q = (char*)c->work_mem.p;
+    auto take = [&](int64_t nf) {
+      double* p = (double*)q;
+      q += nf * fb;
+      return p;
+    };
+    c->G = take(ncomp);
+    c->F = take(ncomp);
+    c->U2 = take(ncomp);
+    c->U3 = take(ncomp);
+    c->W = take(ncomp);
+    c->D = take(ncomp);
+    // within G..D, component cc sits at +cc*N; fb-rounding applies per pair
+    for (int cc = 0; cc < ncomp; ++cc)
+      for (int k = 0; k < ny; ++k) {
+        c->Y1[cc][k] = take(1);
+        if (d == 3) c->Y2[cc][k] = take(1);
+        else c->Y2[cc][k] = nullptr;
+      }
+    c->norm_ws = (double*)q;
+  }
+  if ((rc = build_bank(c, s)) != SETD_OK) return fail(rc);
+  *out = c;
+  return SETD_OK;
+}
+
+int setd_ctx_destroy(setd_ctx* ctx) {
+  clear_error();
+  if (!ctx) return SETD_OK;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return SETD_OK;
+}
+
+int setd_split_phi_apply(setd_ctx* c, int comp, int ell, int stage, const double* V, double* W, double scale,
+                         double beta, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(c != nullptr, "ctx is NULL");
+  SETD_CHECK_ARG(comp >= 0 && comp < c->ncomp, "comp %d outside 0..%d", comp, c->ncomp - 1);
+  SETD_CHECK_ARG(ell == 1 || ell == 2, "ell must be 1 or 2");
+  SETD_CHECK_ARG(stage == SETD_STAGE_2 || stage == SETD_STAGE_3 || stage == SETD_STAGE_F, "bad stage %d", stage);
+  const int e = bank_index(stage, ell);
+  SETD_CHECK_ARG(e >= 0, "stage 2 uses phi_1 only");
+  SETD_CHECK_ARG(V != nullptr && W != nullptr, "V and W must be non-NULL");
+  SETD_CHECK_ARG(!overlap(V, c->N * 8, W, c->N * 8), "V and W overlap");
+  if (!std::isfinite(scale) || !std::isfinite(beta)) {
+    set_error("scale/beta not finite");
+    return SETD_ENONFINITE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const double* base = nullptr;
+  if (beta != 0.0) {
+    if (beta != 1.0) SETD_TRY(launch_scale(W, c->N, beta, s));
+    base = W;
+  }
+  const Splitting& S = c->sp[ell];
+  TuckerOut o;
+  o.Y = W;
+  o.base = base;
+  o.nterms = S.nterms;
+  for (int t = 0; t < S.nterms; ++t) o.term[t] = {V, c->bank[comp][e][t], scale * S.eta[t], c->Y1[0][t], c->Y2[0][t]};
+  return run_tucker_group(c->d, c->dims, &o, 1, s);
+}
+
+int setd_etd_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params, int nparams,
+                  void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(c != nullptr, "ctx is NULL");
+  SETD_CHECK_ARG(u != nullptr, "u is NULL");
+  SETD_CHECK_ARG(nsteps >= 0, "nsteps < 0");
+  SETD_CHECK_ARG(tau > 0.0, "tau must be positive");
+  if (!std::isfinite(tau)) {
+    set_error("tau is not finite");
+    return SETD_ENONFINITE;
+  }
+  GParams gp;
+  SETD_TRY(make_gparams(g_kind, params, nparams, c->ncomp, gp));
+  hipStream_t s = (hipStream_t)stream;
+  if (tau != c->tau) {
+    c->tau = tau;
+    SETD_TRY(build_bank(c, s));
+  }
+  for (int k = 0; k < nsteps; ++k) SETD_TRY(step_once(c, u, gp, s));
+  return SETD_OK;
+}
+
+int setd_field_norms(const double* x, const double* y, int64_t n, double* out, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(x != nullptr && out != nullptr, "x and out must be non-NULL");
+  SETD_CHECK_ARG(n >= 0, "n < 0");
+  if (n == 0) {
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    return SETD_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  SETD_HIP(hipMallocAsync(&ws, norm_workspace_bytes(), s));
+  int rc = launch_norms(x, y, n, (double*)ws, s);
+  double h[4] = {0, 0, 0, 0};
+  if (rc == SETD_OK) {
+    hipError_t e = hipMemcpyAsync(h, (double*)ws + norm_workspace_bytes() / 8 - 4, 4 * sizeof(double),
+                                  hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) {
+      set_error("norm copy failed: %s", hipGetErrorString(e));
+      rc = SETD_EHIP;
+    }
+  }
+  (void)hipFreeAsync(ws, s);
+  if (rc == SETD_OK) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      set_error("sync failed: %s", hipGetErrorString(e));
+      rc = SETD_EHIP;
+    }
+  }
+  for (int k = 0; k < 4; ++k) out[k] = y || k < 2 ? h[k] : 0.0;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every function include/setd.h declares;
+host-side argument validation works without a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2310_07551_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "setd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(setd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("setd_phi_matrices", "setd_tucker_apply", "setd_split_phi_apply", "setd_etd_step",
+                     "setd_ctx_create", "setd_ctx_destroy", "setd_last_error", "setd_sync"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(_lib.SIGNATURES), "binding signatures out of sync with the header"
+
+
+def test_version_and_empty_error():
+    lib = _lib.load()
+    assert b"gfx950" in lib.setd_version()
+    assert lib.setd_last_error() is not None
+
+
+def test_workspace_size_is_host_only():
+    lib = _lib.load()
+    dims = (ctypes.c_int64 * 3)(256, 256, 256)
+    nbytes = lib.setd_tucker_workspace_bytes(3, dims, _lib.PREC_F64)
+    assert nbytes >= 2 * 256 ** 3 * 8
+    assert lib.setd_tucker_workspace_bytes(0, dims, _lib.PREC_F64) == 0
+    bad = (ctypes.c_int64 * 3)(256, 0, 256)
+    assert lib.setd_tucker_workspace_bytes(3, bad, _lib.PREC_F64) == 0
+
+
+def test_validation_errors_before_any_launch():
+    lib = _lib.load()
+    assert lib.setd_phi_matrices(None, 4, 0.1, 1, None, None) == _lib.SETD_EINVAL
+    assert b"non-NULL" in lib.setd_last_error()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int64 * 3)(8, 8, 8)
+    A = (ctypes.c_void_p * 6)()
+    assert lib.setd_ctx_create(ctypes.byref(h), 4, dims, 2, A, 0.01, 0, None) == _lib.SETD_EINVAL
+    assert lib.setd_ctx_create(ctypes.byref(h), 3, dims, 3, A, 0.01, 0, None) == _lib.SETD_EINVAL
+    assert lib.setd_ctx_create(ctypes.byref(h), 3, dims, 2, A, -1.0, 0, None) == _lib.SETD_EINVAL
+    assert lib.setd_ctx_create(ctypes.byref(h), 3, dims, 2, A, 0.01, 0, None) == _lib.SETD_EINVAL   # NULL A
+    assert lib.setd_split_phi_apply(None, 0, 1, 2, None, None, 1.0, 0.0, None) == _lib.SETD_EINVAL
+    p = (ctypes.c_double * 1)(0.0)
+    assert lib.setd_etd_step(None, None, 1, 0.01, 0, p, 0, None) == _lib.SETD_EINVAL
+    dd = (ctypes.c_int64 * 2)(4, 4)
+    M = (ctypes.c_void_p * 2)()
+    assert lib.setd_tucker_apply(None, None, 2, dd, M, 1.0, 0.0, 0, None, 0, None) == _lib.SETD_EINVAL
+    out = (ctypes.c_double * 4)()
+    assert lib.setd_field_norms(None, None, 10, out, None) == _lib.SETD_EINVAL
+
+
+def test_python_binding_raises_on_error():
+    with pytest.raises(_lib.SetdError) as ei:
+        _lib.check(_lib.load().setd_phi_matrices(None, 4, 0.1, 1, None, None))
+    assert ei.value.code == _lib.SETD_EINVAL
