@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""split-ETD3 throughput on one MI355X.
+
+Default workload: 3D FitzHugh-Nagumo on a 256^3 grid (two components, FP64,
+tau = 1e-2; seeded N(0, 0.01^2) initial data), the configuration the metric
+is quoted on.  W warm-up steps, then exactly K timed steps between two device
+synchronisations; the phi bank is built before (its time is reported apart,
+as the paper does).  Prints one JSON line on stdout.
+
+Roofline: while the K steps run, every library kernel launch is bracketed by
+HIP events on the launch stream (setd_profile_*); the dominant kernel class
+(by total time) is reported with its algorithmic flops (2 N n per mode
+product term) divided by its measured time, against the MI355X FP64 matrix
+peak.  cpu_baseline: the FP64 oracle timed on this host for a bounded sample
+of the same workload (one step by default, phi bank excluded).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "split-ETD3 steps/s + Tucker TFLOP/s (%MFMA peak), 3D FHN 256³, FP64 vs split"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mode_flops_per_step(dims, nterms, ncomp=2):
+    """Algorithmic Tucker flops of one step: ncomp x 5 split actions'
+    worth of Tuckers (3 stages of phi_1 on F, phi_2 on D2, phi_2 on D3) x
+    nterms x d mode products x 2 N n_mu."""
+    N = 1
+    for n in dims:
+        N *= n
+    per_tucker = sum(2.0 * N * n for n in dims)
+    return ncomp * 5 * nterms * per_tucker
+
+
+def cpu_baseline(prob, nsteps):
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    banks = oracle.make_banks(prob.A, prob.tau)
+    U = [np.array(x) for x in prob.U0]
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        U = oracle.etd_step(U, prob.A, banks, prob.tau, prob.g_kind, prob.params)
+    dt = time.perf_counter() - t0
+    return dict(value=nsteps / dt, unit="steps/s", cores=threads, kind="oracle",
+                sample="%d step(s) of %s %s (numpy FP64, phi bank excluded), %.1f s" %
+                (nsteps, prob.name, "x".join(map(str, prob.dims)), dt))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fhn3d_256")
+    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the split-ETD3 path here runs on a single MI355X "
+              "(no multi-GPU path is built); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2310_07551_amd as setd
+    import workloads as wl
+
+    prob = wl.make(args.workload)
+    log("workload %s dims %s tau %g" % (prob.name, prob.dims, prob.tau))
+    dev = torch.device("cuda:0")
+    A = [[torch.from_numpy(M.ravel(order="F").copy()).to(dev) for M in Ac] for Ac in prob.A]
+    u = torch.from_numpy(prob.u0_flat()).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = setd.Context(prob.dims, A, prob.tau)
+    torch.cuda.synchronize()
+    phi_s = time.perf_counter() - t0
+    log("phi bank %.3f s" % phi_s)
+
+    ctx.step(u, args.warmup, prob.g_kind, prob.params)
+    torch.cuda.synchronize()
+    setd.profile_enable(True)
+    setd.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(u, args.steps, prob.g_kind, prob.params)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = setd.profile_read(reset=True)
+    setd.profile_enable(False)
+    norms = setd.field_norms(u[:prob.N])
+    if not all(map(lambda x: x == x and abs(x) != float("inf"), norms)):
+        log("non-finite state after the timed steps")
+        sys.exit(1)
+
+    steps_per_s = args.steps / dt
+    nterms = 2 if prob.d == 2 else 3
+    flops_step = mode_flops_per_step(prob.dims, nterms)
+    mode_ms = sum(prof[k]["ms"] for k in ("mode1_f64", "modeB_f64"))
+    mode_flops = sum(prof[k]["flops"] for k in ("mode1_f64", "modeB_f64"))
+    tucker_tflops = mode_flops / (mode_ms * 1e-3) / 1e12 if mode_ms > 0 else 0.0
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    dp = prof[dom]
+    if dp["flops"] > 0:
+        achieved = dp["flops"] / (dp["ms"] * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_TFLOPS["f64"], unit="TFLOP/s",
+                    frac=round(achieved / PEAK_TFLOPS["f64"], 4), traffic=None)
+    else:
+        achieved = dp["bytes"] / (dp["ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None)
+    roof["kernel"] = dom
+    roof["launches"] = dp["launches"]
+    roof["avg_launch_ms"] = round(dp["ms"] / max(1, dp["launches"]), 4)
+
+    kernels = {k: dict(launches=v["launches"], ms_per_step=round(v["ms"] / args.steps, 4),
+                       tflops=round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] > 0 and v["flops"] else None,
+                       gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
+               for k, v in prof.items() if v["launches"]}
+
+    out = {
+        "metric": METRIC,
+        "value": round(steps_per_s, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(prob.dims), "tau": prob.tau, "components": 2,
+                   "kinetics": prob.name, "phi_setup_s": round(phi_s, 3)},
+        "tucker_tflops": round(tucker_tflops, 3),
+        "tucker_frac_peak": round(tucker_tflops / PEAK_TFLOPS["f64"], 4),
+        "tucker_flops_per_step": flops_step,
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (%d step(s))" % args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

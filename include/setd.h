@@ -176,6 +176,25 @@ int setd_etd_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
  */
 int setd_field_norms(const double* x, const double* y, int64_t n, double* out, void* stream);
 
+/*
+ * Kernel timing for measurement.  While enabled, every kernel launch of the
+ * library is bracketed by a pair of hipEvents recorded on the launch stream,
+ * and the launch's algorithmic work is noted: 2 N n flops per mu-mode product
+ * term (N tensor entries, n the contracted size; Section 2 cost count) and
+ * the bytes a single pass must move (inputs read once, outputs written once).
+ * Kernel classes:
+ *   0 mode-1 products, FP64          1 modes >= 2 products, FP64
+ *   2 mode-1 products, FP32/BF16x3   3 modes >= 2 products, FP32/BF16x3
+ *   4 pointwise (G/F, stage differences)
+ * setd_profile_read synchronises the recorded events and writes, per class
+ * c, out[4c..4c+3] = {launches, total milliseconds, total flops, total bytes}
+ * (out is host memory of SETD_PROF_CLASSES*4 doubles); reset != 0 clears the
+ * record.  Enabling costs one event pair per launch.
+ */
+#define SETD_PROF_CLASSES 5
+int setd_profile_enable(int on);
+int setd_profile_read(double* out, int reset);
+
 /* Message for the calling thread's last error ("" if none). */
 const char* setd_last_error(void);
 /* Waits for `stream` and reports an asynchronous HIP error as SETD_EHIP. */

@@ -17,7 +17,7 @@ from ._lib import (G_FHN, G_NONE, G_SCHNAKENBERG, PREC_BF16X3, PREC_F32, PREC_F6
                    SetdError)
 
 __all__ = [
-    "phi_matrices", "tucker_apply", "Context", "field_norms", "colmajor", "version", "SetdError",
+    "phi_matrices", "tucker_apply", "Context", "field_norms", "profile_enable", "profile_read", "colmajor", "version", "SetdError",
     "G_NONE", "G_SCHNAKENBERG", "G_FHN", "PREC_F64", "PREC_F32", "PREC_BF16X3", "STAGE_2", "STAGE_3", "STAGE_F",
 ]
 
@@ -110,6 +110,20 @@ def field_norms(x, y=None, stream=None):
     _lib.check(_lib.load().setd_field_norms(x.data_ptr(), None if y is None else y.data_ptr(), x.numel(), out,
                                             _stream(stream)))
     return tuple(out)
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events (see setd.h)."""
+    _lib.check(_lib.load().setd_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """{class: {"launches", "ms", "flops", "bytes"}} since the last reset."""
+    n = len(_lib.PROF_CLASSES)
+    out = (ctypes.c_double * (4 * n))()
+    _lib.check(_lib.load().setd_profile_read(out, 1 if reset else 0))
+    return {name: dict(launches=int(out[4 * k]), ms=out[4 * k + 1], flops=out[4 * k + 2], bytes=out[4 * k + 3])
+            for k, name in enumerate(_lib.PROF_CLASSES)}
 
 
 class Context:

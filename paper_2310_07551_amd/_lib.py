@@ -47,7 +47,11 @@ SIGNATURES = {
     "setd_last_error": (ctypes.c_char_p, []),
     "setd_sync": (_c_int, [_vp]),
     "setd_version": (ctypes.c_char_p, []),
+    "setd_profile_enable": (_c_int, [_c_int]),
+    "setd_profile_read": (_c_int, [ctypes.POINTER(_c_double), _c_int]),
 }
+
+PROF_CLASSES = ("mode1_f64", "modeB_f64", "mode1_lp", "modeB_lp", "pointwise")
 
 _lib = None
 

@@ -90,6 +90,19 @@ struct ModeJobs {
 
 enum class DType : int { F64 = 0, F32 = 1 };
 
+// ---- kernel timing (setd_profile_*), implemented in setd_api.hip ----
+enum ProfClass : int { kProfMode1F64 = 0, kProfModeBF64 = 1, kProfMode1LP = 2, kProfModeBLP = 3, kProfPointwise = 4 };
+bool prof_on();
+// Records the begin event on construction and the end event on destruction
+// (only while profiling is enabled).
+struct ProfScope {
+  ProfScope(hipStream_t s, int cls, double flops, double bytes);
+  ~ProfScope();
+  hipStream_t s_;
+  int slot_;
+};
+
+
 // Mode-product launchers (implemented in mode_f64.hip / mode_lp.hip).
 // `jobs` is filled by the caller except for the tile fields, which the
 // launcher computes.  All jobs of one launch share regime (mode 1 or not).
@@ -97,6 +110,10 @@ int launch_mode1_f64(ModeJobs& jobs, hipStream_t s);
 int launch_modeB_f64(ModeJobs& jobs, hipStream_t s);
 int launch_mode1_lp(ModeJobs& jobs, int prec, DType in, hipStream_t s);
 int launch_modeB_lp(ModeJobs& jobs, int prec, DType in, DType out, hipStream_t s);
+
+// Algorithmic flops / bytes of a job table (2 N n per term; each input read
+// once, output written once, base read once; es = element sizes in bytes).
+void job_work(const ModeJobs& J, int es_in, int es_out, int es_mat, double& flops, double& bytes);
 
 // Matrix packing (pointwise.hip).
 //   pack_rowmajor: PT[i*ldp + p] = scale*M[i + n p]   (mode-1 operand)

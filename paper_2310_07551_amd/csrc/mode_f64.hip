@@ -334,10 +334,24 @@ int finish_tiles(ModeJobs& J, bool mode1, int TM, int TN) {
     return SETD_OK;                                                                         \
   }
 
+void job_work(const ModeJobs& J, int es_in, int es_out, int es_mat, double& flops, double& bytes) {
+  flops = 0.0;
+  bytes = 0.0;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    const double N = (double)jb.na * jb.n * jb.nb;
+    flops += jb.nterms * 2.0 * N * jb.n;
+    bytes += jb.nterms * (N * es_in + (double)jb.n * jb.n * es_mat) + N * es_out * (jb.base ? 2.0 : 1.0);
+  }
+}
+
 int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
-  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{4, 4});
+  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{4, 2});
   finish_tiles(J, true, cfg.tm, cfg.tn);
   if (J.total_tiles == 0) return SETD_OK;
+  double fl = 0.0, by = 0.0;
+  if (prof_on()) job_work(J, 8, 8, 8, fl, by);
+  ProfScope prof(s, kProfMode1F64, fl, by);
   bool vec = true;
   for (int j = 0; j < J.njobs; ++j) {
     const ModeJob& jb = J.job[j];
@@ -354,9 +368,12 @@ int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
 }
 
 int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
-  const TileCfg cfg = env_tile("SETD_TILE_MODEB", TileCfg{4, 4});
+  const TileCfg cfg = env_tile("SETD_TILE_MODEB", TileCfg{2, 2});
   finish_tiles(J, false, cfg.tm, cfg.tn);
   if (J.total_tiles == 0) return SETD_OK;
+  double fl = 0.0, by = 0.0;
+  if (prof_on()) job_work(J, 8, 8, 8, fl, by);
+  ProfScope prof(s, kProfModeBF64, fl, by);
   bool vec = true;
   for (int j = 0; j < J.njobs; ++j) {
     const ModeJob& jb = J.job[j];

@@ -210,6 +210,8 @@ int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* d
                       const GParams& gp, double* G, void* F, DType ftype, hipStream_t s) {
   const int n3 = d == 3 ? dims[2] : 1;
   const dim3 grid((unsigned)ceil_div(N, 256));
+  // reads u once, writes G (FP64) and F
+  ProfScope prof(s, kProfPointwise, 0.0, (double)N * ncomp * (8 + 8 + (ftype == DType::F64 ? 8 : 4)));
   if (ftype == DType::F64)
     hipLaunchKernelGGL(gf_stencil_kernel<double>, grid, dim3(256), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S,
                        gp, G, (double*)F);
@@ -229,6 +231,8 @@ int launch_g(const double* u, int ncomp, int64_t N, const GParams& gp, double* G
 int launch_stage_d(const double* Us, const double* G, int ncomp, int64_t N, const GParams& gp, void* D,
                    DType dtype, hipStream_t s) {
   const dim3 grid((unsigned)ceil_div(N, 256));
+  // reads Us and G, writes D
+  ProfScope prof(s, kProfPointwise, 0.0, (double)N * ncomp * (8 + 8 + (dtype == DType::F64 ? 8 : 4)));
   if (dtype == DType::F64)
     hipLaunchKernelGGL(stage_d_kernel<double>, grid, dim3(256), 0, s, Us, G, ncomp, N, gp, (double*)D);
   else

@@ -38,6 +38,48 @@ void set_error(const char* fmt, ...) {
 }
 void clear_error() { g_err[0] = 0; }
 
+// ---- kernel timing ----
+namespace {
+struct ProfRec {
+  hipEvent_t b, e;
+  int cls;
+  double flops, bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_free_events;
+
+hipEvent_t get_event() {
+  if (!g_free_events.empty()) {
+    hipEvent_t e = g_free_events.back();
+    g_free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool prof_on() { return g_prof; }
+
+ProfScope::ProfScope(hipStream_t s, int cls, double flops, double bytes) : s_(s), slot_(-1) {
+  if (!g_prof) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfRec r{get_event(), get_event(), cls, flops, bytes};
+  if (!r.b || !r.e) return;
+  if (hipEventRecord(r.b, s) != hipSuccess) return;
+  g_recs.push_back(r);
+  slot_ = (int)g_recs.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+  if (slot_ < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  (void)hipEventRecord(g_recs[slot_].e, s_);
+}
+
 namespace {
 
 // Bank entries of Algorithms 1-2: (stage, ell) pairs.
@@ -417,6 +459,38 @@ extern "C" {
 const char* setd_last_error(void) { return g_err; }
 
 const char* setd_version(void) { return "setd 0.1 (gfx950, FP64 MFMA mode products)"; }
+
+int setd_profile_enable(int on) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof = on != 0;
+  return SETD_OK;
+}
+
+int setd_profile_read(double* out, int reset) {
+  clear_error();
+  SETD_CHECK_ARG(out != nullptr, "out is NULL");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int k = 0; k < 4 * SETD_PROF_CLASSES; ++k) out[k] = 0.0;
+  for (const ProfRec& r : g_recs) {
+    SETD_HIP(hipEventSynchronize(r.e));
+    float ms = 0.0f;
+    SETD_HIP(hipEventElapsedTime(&ms, r.b, r.e));
+    double* o = out + 4 * r.cls;
+    o[0] += 1.0;
+    o[1] += ms;
+    o[2] += r.flops;
+    o[3] += r.bytes;
+  }
+  if (reset) {
+    for (const ProfRec& r : g_recs) {
+      g_free_events.push_back(r.b);
+      g_free_events.push_back(r.e);
+    }
+    g_recs.clear();
+  }
+  return SETD_OK;
+}
 
 int setd_sync(void* stream) {
   clear_error();
