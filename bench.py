@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--workload", default="fhn3d_256")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="f64,f32,bf16x3,bf16x2",
+                    help="arithmetic forms to time (f64 always runs; f32, bf16x3, bf16x2 are compared against it)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -89,29 +91,51 @@ def main():
     log("workload %s dims %s tau %g" % (prob.name, prob.dims, prob.tau))
     dev = torch.device("cuda:0")
     A = [[torch.from_numpy(M.ravel(order="F").copy()).to(dev) for M in Ac] for Ac in prob.A]
-    u = torch.from_numpy(prob.u0_flat()).to(dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx = setd.Context(prob.dims, A, prob.tau)
-    torch.cuda.synchronize()
-    phi_s = time.perf_counter() - t0
-    log("phi bank %.3f s" % phi_s)
+    u0 = torch.from_numpy(prob.u0_flat()).to(dev)
 
-    ctx.step(u, args.warmup, prob.g_kind, prob.params)
-    torch.cuda.synchronize()
-    setd.profile_enable(True)
-    setd.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(u, args.steps, prob.g_kind, prob.params)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = setd.profile_read(reset=True)
-    setd.profile_enable(False)
+    def run_form(prec, steps, warmup):
+        """phi bank, W warm-up steps, K timed steps (events on); returns
+        (phi seconds, timed seconds, per-class profile, final state)."""
+        u = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = setd.Context(prob.dims, A, prob.tau, prec=prec)
+        torch.cuda.synchronize()
+        phi = time.perf_counter() - t0
+        ctx.step(u, warmup, prob.g_kind, prob.params)
+        torch.cuda.synchronize()
+        setd.profile_enable(True)
+        setd.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(u, steps, prob.g_kind, prob.params)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = setd.profile_read(reset=True)
+        setd.profile_enable(False)
+        ctx.close()
+        return phi, dt, prof, u
+
+    phi_s, dt, prof, u = run_form(setd.PREC_F64, args.steps, args.warmup)
+    log("phi bank %.3f s, %d steps in %.3f s" % (phi_s, args.steps, dt))
     norms = setd.field_norms(u[:prob.N])
     if not all(map(lambda x: x == x and abs(x) != float("inf"), norms)):
         log("non-finite state after the timed steps")
         sys.exit(1)
+
+    forms = {}
+    for name in [f for f in args.forms.split(",") if f and f != "f64"]:
+        prec = {"f32": setd.PREC_F32, "bf16x3": setd.PREC_BF16X3, "bf16x2": setd.PREC_BF16X2}[name]
+        phi_l, dt_l, prof_l, u_l = run_form(prec, args.steps, args.warmup)
+        errs = [setd.field_norms(u_l[c * prob.N:(c + 1) * prob.N], u[c * prob.N:(c + 1) * prob.N]) for c in range(2)]
+        ms = sum(prof_l[k]["ms"] for k in ("mode1_lp", "modeB_lp"))
+        fl = sum(prof_l[k]["flops"] for k in ("mode1_lp", "modeB_lp"))
+        forms[name] = dict(steps_per_s=round(args.steps / dt_l, 4), ms_per_step=round(dt_l / args.steps * 1e3, 4),
+                           speedup_vs_f64=round(dt / dt_l, 3),
+                           rel_l2_vs_f64=[e[2] / e[0] for e in errs],
+                           tucker_tflops=round(fl / (ms * 1e-3) / 1e12, 3) if ms > 0 else None,
+                           phi_setup_s=round(phi_l, 3))
+        log("%s: %.2f steps/s, rel_l2 vs f64 %s" % (name, args.steps / dt_l, forms[name]["rel_l2_vs_f64"]))
 
     steps_per_s = args.steps / dt
     nterms = 2 if prob.d == 2 else 3
@@ -157,6 +181,7 @@ def main():
         "tucker_frac_peak": round(tucker_tflops / PEAK_TFLOPS["f64"], 4),
         "tucker_flops_per_step": flops_step,
         "kernels": kernels,
+        "precision_forms": forms,
         "roofline": roof,
         "cpu_baseline": None,
     }

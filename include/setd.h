@@ -51,8 +51,12 @@ extern "C" {
 /* ---- arithmetic of the mu-mode products ---- */
 #define SETD_PREC_F64     0    /* FP64 operands, FP64 accumulate                */
 #define SETD_PREC_F32     1    /* FP32 operands and intermediates, FP32 accum.  */
-#define SETD_PREC_BF16X3  2    /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi on
-                                  MFMA with FP32 accumulate; FP32 intermediates */
+#define SETD_PREC_BF16X3  2    /* three-term bf16 split x = h + m + l (each the
+                                  bf16 rounding of what is left); the six
+                                  products h*h, h*m, m*h, h*l, l*h, m*m on MFMA
+                                  with FP32 accumulate; FP32 intermediates     */
+#define SETD_PREC_BF16X2  3    /* two-term split x = h + l; h*h, h*l, l*h (three
+                                  products): faster, about 16 significant bits */
 
 /* ---- reaction terms g (eq. twocompdisc: two components u, v) ---- */
 #define SETD_G_NONE         0  /* g = 0; nparams = 0                            */

@@ -21,6 +21,7 @@ SETD_EUNSUPPORTED = -5
 PREC_F64 = 0
 PREC_F32 = 1
 PREC_BF16X3 = 2
+PREC_BF16X2 = 3
 
 G_NONE = 0
 G_SCHNAKENBERG = 1

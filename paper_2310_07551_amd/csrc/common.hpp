@@ -86,7 +86,21 @@ struct ModeJobs {
   ModeJob job[kMaxJobs];
   int njobs;
   int64_t total_tiles;
+  int64_t tiles_per_job;   // > 0 when every job has this many tiles
 };
+
+// Job owning logical tile t: one division when all jobs have the same tile
+// count, else a binary search over tile_begin (no serial chain of loads).
+__device__ __forceinline__ int find_job(const ModeJobs& J, int64_t t) {
+  if (J.tiles_per_job > 0) return (int)(t / J.tiles_per_job);
+  int lo = 0, hi = J.njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (J.job[mid].tile_begin <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 enum class DType : int { F64 = 0, F32 = 1 };
 
@@ -108,8 +122,10 @@ struct ProfScope {
 // launcher computes.  All jobs of one launch share regime (mode 1 or not).
 int launch_mode1_f64(ModeJobs& jobs, hipStream_t s);
 int launch_modeB_f64(ModeJobs& jobs, hipStream_t s);
-int launch_mode1_lp(ModeJobs& jobs, int prec, DType in, hipStream_t s);
-int launch_modeB_lp(ModeJobs& jobs, int prec, DType in, DType out, hipStream_t s);
+// Reduced precision (mode_lp.hip): FP32 tensor inputs, output FP32 or FP64
+// (FP64 output adds the optional FP64 base).
+int launch_mode1_lp(ModeJobs& jobs, int prec, DType out, hipStream_t s);
+int launch_modeB_lp(ModeJobs& jobs, int prec, DType out, hipStream_t s);
 
 // Algorithmic flops / bytes of a job table (2 N n per term; each input read
 // once, output written once, base read once; es = element sizes in bytes).
@@ -121,7 +137,10 @@ void job_work(const ModeJobs& J, int es_in, int es_out, int es_mat, double& flop
 // zero outside n x n.
 int pack_matrix_f64(const double* M, int n, double scale, bool rowmajor, double* out, hipStream_t s);
 int pack_matrix_f32(const double* M, int n, double scale, bool rowmajor, float* out, hipStream_t s);
-int pack_matrix_bf16x2(const double* M, int n, double scale, bool rowmajor, void* out, hipStream_t s);
+int pack_matrix_bf16(const double* M, int n, double scale, bool rowmajor, int np, void* out, hipStream_t s);
+inline bool is_prec(int p) {
+  return p == SETD_PREC_F64 || p == SETD_PREC_F32 || p == SETD_PREC_BF16X3 || p == SETD_PREC_BF16X2;
+}
 size_t packed_bytes(int n, int prec);
 
 // Pointwise helpers (pointwise.hip).

@@ -39,12 +39,6 @@ __device__ __forceinline__ int64_t remap_xcd(int64_t bid, int64_t per_xcd) {
   return (bid & 7) * per_xcd + (bid >> 3);
 }
 
-__device__ __forceinline__ int find_job(const ModeJobs& J, int64_t t) {
-  int j = 0;
-  while (j + 1 < J.njobs && J.job[j + 1].tile_begin <= t) ++j;
-  return j;
-}
-
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -309,6 +303,9 @@ int finish_tiles(ModeJobs& J, bool mode1, int TM, int TN) {
     tot += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
   }
   J.total_tiles = tot;
+  J.tiles_per_job = J.njobs > 0 ? tot / J.njobs : 0;
+  for (int j = 0; j < J.njobs; ++j)
+    if (J.job[j].tile_begin != (int64_t)j * J.tiles_per_job) J.tiles_per_job = 0;
   return SETD_OK;
 }
 

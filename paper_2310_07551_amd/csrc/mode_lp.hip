@@ -1,0 +1,539 @@
+// Reduced-precision mu-mode products (same operation and job tables as
+// mode_f64.hip): operands and intermediates in FP32, the last mode of a
+// Tucker written in FP64 on top of an FP64 base.
+//
+//   SETD_PREC_F32     v_mfma_f32_16x16x4f32, FP32 accumulate.
+//   SETD_PREC_BF16X3  v_mfma_f32_16x16x32_bf16 with the three-term split
+//                     x = h + m + l (h = bf16(x), m = bf16(x - h),
+//                     l = bf16(x - h - m)) and the six products of order
+//                     <= 2^-16: hh + hm + mh + hl + lh + mm, FP32 accumulate
+//                     (about FP32 accuracy).
+//   SETD_PREC_BF16X2  the two-term split x = h + l with hh + hl + lh (about
+//                     16 significant bits, half the matrix-core work).
+//                     The matrix is split once when it is packed; the tensor
+//                     operand is split in registers right after its load.
+//
+// Per-term scale factors multiply the FP32 tensor operand before any split,
+// so they never cost bf16 precision.
+//
+// Operand layouts (probed on gfx950): FP32 16x16x4 and BF16 16x16x32 put
+// tile row 4 g + r in register r of lane (g, l); in the bf16 form lane (g, l)
+// supplies A[l][8 g + j] and B[8 g + j][l] in slot j.
+//
+// mode 1 (contraction index contiguous):  MFMA rows = i (matrix, packed
+//   row-major), columns = b (tensor columns), k = p.
+// modes >= 2:  MFMA rows = a (contiguous tensor index), columns = i, k = p;
+//   the FP32 form reads the matrix column-major packed, the bf16 form
+//   row-major packed (it needs 8 consecutive p of one row per lane).
+#include "common.hpp"
+
+#include <cstdlib>
+
+namespace setd {
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int64_t remap_xcd_lp(int64_t bid, int64_t per_xcd) {
+  return (bid & 7) * per_xcd + (bid >> 3);
+}
+
+__device__ __forceinline__ int find_job_lp(const ModeJobs& J, int64_t t) { return find_job(J, t); }
+
+// x = p[0] + p[1] (+ p[2]): each piece the bf16 rounding (RNE) of the FP32
+// remainder left by the previous ones.
+template <int NP>
+__device__ __forceinline__ void split_bf16(const f8& x, bf8 (&p)[NP]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    float r = x[j];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const __bf16 h = (__bf16)r;
+      p[k][j] = h;
+      r -= (float)h;
+    }
+  }
+}
+
+__device__ __forceinline__ f4 mfma_bf(const bf8& a, const bf8& b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Cross products of order <= 2^-8 (NP = 2) or <= 2^-16 (NP = 3), smallest
+// first so the FP32 accumulator adds them before the leading term.
+template <int NP>
+__device__ __forceinline__ f4 mfma_split(const bf8 (&a)[NP], const bf8 (&b)[NP], f4 c) {
+  if constexpr (NP == 3) {
+    c = mfma_bf(a[1], b[1], c);
+    c = mfma_bf(a[0], b[2], c);
+    c = mfma_bf(a[2], b[0], c);
+  }
+  c = mfma_bf(a[0], b[1], c);
+  c = mfma_bf(a[1], b[0], c);
+  c = mfma_bf(a[0], b[0], c);
+  return c;
+}
+
+// Writes `cnt` consecutive results starting at Y + off (all in range when
+// full) as FP32 or, for an FP64 output, base + value.
+template <typename TOut>
+__device__ __forceinline__ void store_run(TOut* __restrict__ Y, const double* __restrict__ base, int64_t off,
+                                          const float* v, int cnt, int valid, bool vec) {
+  if (vec && valid >= cnt) {
+    if constexpr (sizeof(TOut) == 4) {
+      for (int e = 0; e < cnt; e += 4) *(f4*)(Y + off + e) = f4{v[e], v[e + 1], v[e + 2], v[e + 3]};
+    } else {
+      for (int e = 0; e < cnt; e += 2) {
+        d2 w = d2{(double)v[e], (double)v[e + 1]};
+        if (base) w += *(const d2*)(base + off + e);
+        *(d2*)(Y + off + e) = w;
+      }
+    }
+  } else {
+    for (int e = 0; e < cnt; ++e) {
+      if (e < valid) {
+        if constexpr (sizeof(TOut) == 4) {
+          Y[off + e] = v[e];
+        } else {
+          double w = (double)v[e];
+          if (base) w += base[off + e];
+          Y[off + e] = w;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32, mode 1
+// ---------------------------------------------------------------------------
+template <int TM, int TN, bool VEC, typename TOut>
+__global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const ModeJob& jb = J.job[find_job_lp(J, t)];
+  const int64_t lt = t - jb.tile_begin;
+  const int it = (int)(lt % jb.tiles_i);
+  const int64_t bt = lt / jb.tiles_i;
+  const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+  const int n = jb.n, ldp = jb.ldp;
+  const int64_t nb = jb.nb;
+  const int i0 = it * 16 * TM;
+  const int64_t b0 = bt * 16 * TN;
+  const float* __restrict__ X = (const float*)jb.X[0];
+  const float* __restrict__ PT = (const float*)jb.P[0];
+  const float sc = (float)jb.scale[0];
+
+  const float* pa[TM];
+#pragma unroll
+  for (int m = 0; m < TM; ++m) pa[m] = PT + (int64_t)(i0 + TM * l + m) * ldp + 4 * g;
+  const float* pb[TN];
+  bool vb[TN];
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int64_t b = b0 + 16 * u + l;
+    vb[u] = b < nb;
+    pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + 4 * g;
+  }
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+
+  auto load = [&](int p0, f4* ar, f4* br) {
+#pragma unroll
+    for (int m = 0; m < TM; ++m) ar[m] = *(const f4*)(pa[m] + p0);
+    const bool full = VEC && (p0 + 16 <= n);
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      if (full) {
+        br[u] = vb[u] ? *(const f4*)(pb[u] + p0) * sc : f4{0.f, 0.f, 0.f, 0.f};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] * sc : 0.f;
+      }
+    }
+  };
+  f4 a[TM], bx[TN];
+  load(0, a, bx);
+  for (int p0 = 0; p0 < n; p0 += 16) {
+    f4 an[TM], bn[TN];
+    const bool more = p0 + 16 < n;
+    if (more) load(p0 + 16, an, bn);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+#pragma unroll
+        for (int u = 0; u < TN; ++u)
+          acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][jj], bx[u][jj], acc[m][u], 0, 0, 0);
+    if (more) {
+#pragma unroll
+      for (int m = 0; m < TM; ++m) a[m] = an[m];
+#pragma unroll
+      for (int u = 0; u < TN; ++u) bx[u] = bn[u];
+    }
+  }
+  // tile row q = 4 g + r -> output row i0 + TM q + m: lane (g, l) owns the
+  // 4 TM consecutive rows i0 + 4 TM g + (TM r + m) of column b0 + 16 u + l.
+  TOut* __restrict__ Y = (TOut*)jb.Y;
+  const double* __restrict__ base = (const double*)jb.base;
+  const int ir = i0 + 4 * TM * g;
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    if (!vb[u]) continue;
+    float v[4 * TM];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r];
+    store_run<TOut>(Y, base, (b0 + 16 * u + l) * (int64_t)n + ir, v, 4 * TM, n - ir, VEC);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32, modes >= 2
+// ---------------------------------------------------------------------------
+template <int TM, int TN, bool VEC, typename TOut>
+__global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const ModeJob& jb = J.job[find_job_lp(J, t)];
+  const int64_t lt = t - jb.tile_begin;
+  const int it = (int)(lt % jb.tiles_i);
+  const int64_t rest = lt / jb.tiles_i;
+  const int64_t at = rest % jb.tiles_a;
+  const int64_t b = rest / jb.tiles_a;
+  const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+  const int n = jb.n, ldp = jb.ldp, nterms = jb.nterms;
+  const int64_t na = jb.na;
+  const int64_t a0 = at * 16 * TM;
+  const int i0 = it * 16 * TN;
+  const int64_t arow = a0 + TM * l;
+  const bool lane_full = arow + TM <= na;
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t slab = na * (int64_t)n * b;
+  for (int term = 0; term < nterms; ++term) {
+    const float* __restrict__ xb = (const float*)jb.X[term] + slab + arow + na * g;
+    const float* __restrict__ pbp = (const float*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
+    const float sc = (float)jb.scale[term];
+    auto load = [&](int p0, float* xr, float* pr) {
+      const bool vp = p0 + g < n;
+      const float* xs = xb + na * (int64_t)p0;
+      if (VEC && TM == 4 && lane_full && vp) {
+        const f4 v = *(const f4*)xs * sc;
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = v[m];
+      } else if (VEC && TM == 2 && lane_full && vp) {
+        const f2 v = *(const f2*)xs * sc;
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = v[m];
+      } else {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = (vp && arow + m < na) ? xs[m] * sc : 0.f;
+      }
+      const float* ps = pbp + (int64_t)ldp * p0;
+#pragma unroll
+      for (int u = 0; u < TN; ++u) pr[u] = ps[u];
+    };
+    float xr[TM], pr[TN];
+    load(0, xr, pr);
+    for (int p0 = 0; p0 < n; p0 += 4) {
+      float xn[TM], pn[TN];
+      const bool more = p0 + 4 < n;
+      if (more) load(p0 + 4, xn, pn);
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+#pragma unroll
+        for (int u = 0; u < TN; ++u)
+          acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[m], pr[u], acc[m][u], 0, 0, 0);
+      if (more) {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) xr[m] = xn[m];
+#pragma unroll
+        for (int u = 0; u < TN; ++u) pr[u] = pn[u];
+      }
+    }
+  }
+  // lane (g, l) owns a = a0 + 4 TM g + (TM r + m) of column i0 + TN l + u
+  TOut* __restrict__ Y = (TOut*)jb.Y;
+  const double* __restrict__ base = (const double*)jb.base;
+  const int64_t ar = a0 + 4 * TM * g;
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int i = i0 + TN * l + u;
+    if (i >= n) continue;
+    float v[4 * TM];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r];
+    store_run<TOut>(Y, base, slab + na * (int64_t)i + ar, v, 4 * TM, (int)(na - ar < 4 * TM ? na - ar : 4 * TM),
+                    VEC);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3, mode 1: k-chunks of 32; lane group g holds p0 + 8 g + (0..7)
+// ---------------------------------------------------------------------------
+template <int NP, int TM, int TN, bool VEC, typename TOut>
+__global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const ModeJob& jb = J.job[find_job_lp(J, t)];
+  const int64_t lt = t - jb.tile_begin;
+  const int it = (int)(lt % jb.tiles_i);
+  const int64_t bt = lt / jb.tiles_i;
+  const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+  const int n = jb.n, ldp = jb.ldp;
+  const int64_t nb = jb.nb;
+  const int64_t plane = (int64_t)ldp * ldp;
+  const int i0 = it * 16 * TM;
+  const int64_t b0 = bt * 16 * TN;
+  const float* __restrict__ X = (const float*)jb.X[0];
+  const __bf16* __restrict__ PH = (const __bf16*)jb.P[0];
+  const float sc = (float)jb.scale[0];
+
+  int64_t poff[TM];
+#pragma unroll
+  for (int m = 0; m < TM; ++m) poff[m] = (int64_t)(i0 + TM * l + m) * ldp + 8 * g;
+  const float* pb[TN];
+  bool vb[TN];
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int64_t b = b0 + 16 * u + l;
+    vb[u] = b < nb;
+    pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + 8 * g;
+  }
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int p0 = 0; p0 < n; p0 += 32) {
+    bf8 ap[TM][NP], bp[TN][NP];
+#pragma unroll
+    for (int m = 0; m < TM; ++m)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) ap[m][k] = *(const bf8*)(PH + k * plane + poff[m] + p0);
+    const bool full = VEC && (p0 + 32 <= n);
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      f8 x;
+      if (full && vb[u]) {
+        x = *(const f8*)(pb[u] + p0) * sc;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = (vb[u] && p0 + 8 * g + e < n) ? pb[u][p0 + e] * sc : 0.f;
+      }
+      split_bf16<NP>(x, bp[u]);
+    }
+#pragma unroll
+    for (int m = 0; m < TM; ++m)
+#pragma unroll
+      for (int u = 0; u < TN; ++u) acc[m][u] = mfma_split<NP>(ap[m], bp[u], acc[m][u]);
+  }
+  TOut* __restrict__ Y = (TOut*)jb.Y;
+  const double* __restrict__ base = (const double*)jb.base;
+  const int ir = i0 + 4 * TM * g;
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    if (!vb[u]) continue;
+    float v[4 * TM];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r];
+    store_run<TOut>(Y, base, (b0 + 16 * u + l) * (int64_t)n + ir, v, 4 * TM, n - ir, VEC);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3, modes >= 2
+// ---------------------------------------------------------------------------
+template <int NP, int TM, int TN, bool VEC, typename TOut>
+__global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const ModeJob& jb = J.job[find_job_lp(J, t)];
+  const int64_t lt = t - jb.tile_begin;
+  const int it = (int)(lt % jb.tiles_i);
+  const int64_t rest = lt / jb.tiles_i;
+  const int64_t at = rest % jb.tiles_a;
+  const int64_t b = rest / jb.tiles_a;
+  const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+  const int n = jb.n, ldp = jb.ldp, nterms = jb.nterms;
+  const int64_t na = jb.na;
+  const int64_t plane = (int64_t)ldp * ldp;
+  const int64_t a0 = at * 16 * TM;
+  const int i0 = it * 16 * TN;
+  const int64_t arow = a0 + TM * l;
+  const bool lane_full = arow + TM <= na;
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t slab = na * (int64_t)n * b;
+  for (int term = 0; term < nterms; ++term) {
+    const float* __restrict__ xb = (const float*)jb.X[term] + slab + arow;
+    const __bf16* __restrict__ PH = (const __bf16*)jb.P[term];
+    const float sc = (float)jb.scale[term];
+    for (int p0 = 0; p0 < n; p0 += 32) {
+      // tensor operand: 8 p values (8 g + j) x TM rows per lane
+      f8 xm[TM];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int p = p0 + 8 * g + j;
+        const bool vp = p < n;
+        const float* xs = xb + na * (int64_t)p;
+        if (VEC && TM == 4 && lane_full && vp) {
+          const f4 v = *(const f4*)xs;
+#pragma unroll
+          for (int m = 0; m < TM; ++m) xm[m][j] = v[m] * sc;
+        } else if (VEC && TM == 2 && lane_full && vp) {
+          const f2 v = *(const f2*)xs;
+#pragma unroll
+          for (int m = 0; m < TM; ++m) xm[m][j] = v[m] * sc;
+        } else {
+#pragma unroll
+          for (int m = 0; m < TM; ++m) xm[m][j] = (vp && arow + m < na) ? xs[m] * sc : 0.f;
+        }
+      }
+      bf8 ap[TM][NP], bp[TN][NP];
+#pragma unroll
+      for (int m = 0; m < TM; ++m) split_bf16<NP>(xm[m], ap[m]);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) {
+        const int64_t off = (int64_t)(i0 + TN * l + u) * ldp + p0 + 8 * g;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) bp[u][k] = *(const bf8*)(PH + k * plane + off);
+      }
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+#pragma unroll
+        for (int u = 0; u < TN; ++u) acc[m][u] = mfma_split<NP>(ap[m], bp[u], acc[m][u]);
+    }
+  }
+  TOut* __restrict__ Y = (TOut*)jb.Y;
+  const double* __restrict__ base = (const double*)jb.base;
+  const int64_t ar = a0 + 4 * TM * g;
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int i = i0 + TN * l + u;
+    if (i >= n) continue;
+    float v[4 * TM];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r];
+    store_run<TOut>(Y, base, slab + na * (int64_t)i + ar, v, 4 * TM, (int)(na - ar < 4 * TM ? na - ar : 4 * TM),
+                    VEC);
+  }
+}
+
+int finish_tiles_lp(ModeJobs& J, bool mode1, int TM, int TN) {
+  int64_t tot = 0;
+  for (int j = 0; j < J.njobs; ++j) {
+    ModeJob& jb = J.job[j];
+    if (mode1) {
+      jb.tiles_i = (int)ceil_div(jb.n, 16 * TM);
+      jb.tiles_a = (int)ceil_div(jb.nb, 16 * TN);
+    } else {
+      jb.tiles_i = (int)ceil_div(jb.n, 16 * TN);
+      jb.tiles_a = (int)ceil_div(jb.na, 16 * TM);
+    }
+    jb.tile_begin = tot;
+    tot += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
+  }
+  J.total_tiles = tot;
+  J.tiles_per_job = J.njobs > 0 ? tot / J.njobs : 0;
+  for (int j = 0; j < J.njobs; ++j)
+    if (J.job[j].tile_begin != (int64_t)j * J.tiles_per_job) J.tiles_per_job = 0;
+  return SETD_OK;
+}
+
+bool aligned_lp(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+constexpr int kTM1 = 4, kTN1 = 2;   // mode 1 wave tile (rows x columns of 16)
+constexpr int kTMB = 2, kTNB = 2;   // modes >= 2
+
+}  // namespace
+
+namespace {
+
+template <bool VEC, typename T>
+void go_mode1(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  if (prec == SETD_PREC_F32)
+    hipLaunchKernelGGL((mode1_f32_kernel<kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
+  else if (prec == SETD_PREC_BF16X3)
+    hipLaunchKernelGGL((mode1_bf16_kernel<3, kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
+  else
+    hipLaunchKernelGGL((mode1_bf16_kernel<2, kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
+}
+
+template <bool VEC, typename T>
+void go_modeB(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  if (prec == SETD_PREC_F32)
+    hipLaunchKernelGGL((modeB_f32_kernel<kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
+  else if (prec == SETD_PREC_BF16X3)
+    hipLaunchKernelGGL((modeB_bf16_kernel<3, kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
+  else
+    hipLaunchKernelGGL((modeB_bf16_kernel<2, kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
+}
+
+}  // namespace
+
+int launch_mode1_lp(ModeJobs& J, int prec, DType out, hipStream_t s) {
+  finish_tiles_lp(J, true, kTM1, kTN1);
+  if (J.total_tiles == 0) return SETD_OK;
+  const int kc = prec == SETD_PREC_F32 ? 4 : 8;     // contiguous p per lane
+  bool vec = true;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    vec = vec && (jb.n % kc == 0) && aligned_lp(jb.X[0], 4 * kc) && aligned_lp(jb.Y, 16) && aligned_lp(jb.base, 16);
+  }
+  double fl = 0.0, by = 0.0;
+  if (prof_on()) job_work(J, 4, out == DType::F64 ? 8 : 4, 4, fl, by);
+  ProfScope prof(s, kProfMode1LP, fl, by);
+  const int64_t per = ceil_div(J.total_tiles, 8);
+  const dim3 grid((unsigned)(per * 8));
+  if (out == DType::F32)
+    vec ? go_mode1<true, float>(prec, grid, s, J, per) : go_mode1<false, float>(prec, grid, s, J, per);
+  else
+    vec ? go_mode1<true, double>(prec, grid, s, J, per) : go_mode1<false, double>(prec, grid, s, J, per);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int launch_modeB_lp(ModeJobs& J, int prec, DType out, hipStream_t s) {
+  finish_tiles_lp(J, false, kTMB, kTNB);
+  if (J.total_tiles == 0) return SETD_OK;
+  bool vec = true;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    vec = vec && (jb.na % 4 == 0) && aligned_lp(jb.Y, 16) && aligned_lp(jb.base, 16);
+    for (int t = 0; t < jb.nterms; ++t) vec = vec && aligned_lp(jb.X[t], 16);
+  }
+  double fl = 0.0, by = 0.0;
+  if (prof_on()) job_work(J, 4, out == DType::F64 ? 8 : 4, 4, fl, by);
+  ProfScope prof(s, kProfModeBLP, fl, by);
+  const int64_t per = ceil_div(J.total_tiles, 8);
+  const dim3 grid((unsigned)(per * 8));
+  if (out == DType::F32)
+    vec ? go_modeB<true, float>(prec, grid, s, J, per) : go_modeB<false, float>(prec, grid, s, J, per);
+  else
+    vec ? go_modeB<true, double>(prec, grid, s, J, per) : go_modeB<false, double>(prec, grid, s, J, per);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+}  // namespace setd

@@ -30,8 +30,9 @@ __global__ void pack_kernel(const double* __restrict__ M, int n, int ldp, double
   out[idx] = (T)v;
 }
 
-// bf16 split: the packed buffer holds ldp*ldp hi values followed by ldp*ldp
-// lo values (round-to-nearest-even; x ~ hi + lo).
+// bf16 split: the packed buffer holds np planes of ldp*ldp bf16 values,
+// plane k the round-to-nearest-even bf16 of what planes 0..k-1 leave of the
+// (FP64) matrix entry, so the entry is ~ the sum of its np pieces.
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
   uint32_t lsb = (u >> 16) & 1u;
@@ -40,26 +41,27 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__global__ void pack_bf16x2_kernel(const double* __restrict__ M, int n, int ldp, double scale, bool rowmajor,
-                                   uint16_t* __restrict__ out) {
+__global__ void pack_bf16_kernel(const double* __restrict__ M, int n, int ldp, double scale, bool rowmajor, int np,
+                                 uint16_t* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tot = (int64_t)ldp * ldp;
   if (idx >= tot) return;
   const int r = (int)(idx % ldp), c = (int)(idx / ldp);
   const int i = rowmajor ? c : r, p = rowmajor ? r : c;
-  const double v = (i < n && p < n) ? scale * M[i + (int64_t)n * p] : 0.0;
-  const float vf = (float)v;
-  const uint16_t hi = f32_to_bf16_rne(vf);
-  const uint16_t lo = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(hi)));
-  out[idx] = hi;
-  out[tot + idx] = lo;
+  double rem = (i < n && p < n) ? scale * M[i + (int64_t)n * p] : 0.0;
+  for (int k = 0; k < np; ++k) {
+    const uint16_t h = f32_to_bf16_rne((float)rem);
+    out[k * tot + idx] = h;
+    rem -= (double)bf16_to_f32(h);
+  }
 }
 
 size_t packed_bytes(int n, int prec) {
   const size_t e = (size_t)packed_ld(n) * packed_ld(n);
   if (prec == SETD_PREC_F64) return e * 8;
   if (prec == SETD_PREC_F32) return e * 4;
-  return e * 4;   // two bf16 planes
+  if (prec == SETD_PREC_BF16X3) return e * 6;   // three bf16 planes
+  return e * 4;                                 // two bf16 planes
 }
 
 int pack_matrix_f64(const double* M, int n, double scale, bool rowmajor, double* out, hipStream_t s) {
@@ -80,11 +82,11 @@ int pack_matrix_f32(const double* M, int n, double scale, bool rowmajor, float* 
   return SETD_OK;
 }
 
-int pack_matrix_bf16x2(const double* M, int n, double scale, bool rowmajor, void* out, hipStream_t s) {
+int pack_matrix_bf16(const double* M, int n, double scale, bool rowmajor, int np, void* out, hipStream_t s) {
   const int ldp = packed_ld(n);
   const int64_t tot = (int64_t)ldp * ldp;
-  hipLaunchKernelGGL(pack_bf16x2_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, M, n, ldp, scale,
-                     rowmajor, (uint16_t*)out);
+  hipLaunchKernelGGL(pack_bf16_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, M, n, ldp, scale,
+                     rowmajor, np, (uint16_t*)out);
   SETD_LAUNCHED();
   return SETD_OK;
 }

@@ -17,6 +17,7 @@
 // (eqs. split2d / splitnd3) costs nterms Tuckers of d mu-mode products.
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -135,8 +136,20 @@ struct setd_ctx {
   double *G = nullptr, *F = nullptr, *U2 = nullptr, *U3 = nullptr, *W = nullptr, *D = nullptr;
   double* Y1[2][9] = {};
   double* Y2[2][9] = {};
-  double* norm_ws = nullptr;
+  double* aux = nullptr;         // FP32 copy of a split_phi_apply input (reduced precision)
   DevBuf A_mem, stencil_mem, bank_mem, work_mem;
+  // one captured step (hipGraph), replayed per step on an internal stream
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  double* g_u = nullptr;
+  GParams g_gp{};
+  ~setd_ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
 };
 
 namespace {
@@ -159,11 +172,11 @@ ModeJob mk_job(const void* X, const void* P, double scale, void* Y, const void* 
 
 // One Tucker-summed output: Y = base + sum_t scale_t T(X_t, {P_t[mu]}).
 struct TuckerTerm {
-  const double* X;
-  void* const* P;       // d packed matrices (mode 1 row-major, others column-major)
+  const void* X;        // FP64, or FP32 for the reduced-precision forms
+  void* const* P;       // d packed matrices (layout per pack_for)
   double scale;
-  double* Y1;
-  double* Y2;
+  void* Y1;             // intermediates, same type as X
+  void* Y2;
 };
 struct TuckerOut {
   double* Y;
@@ -172,33 +185,58 @@ struct TuckerOut {
   TuckerTerm term[kMaxTerms];
 };
 
-int flush(ModeJobs& J, bool mode1, hipStream_t s) {
+// How a table of jobs is launched: which regime, which arithmetic, and the
+// output type (FP64 for the last mode of a Tucker; the reduced-precision
+// forms keep their intermediates in FP32).
+struct LaunchKind {
+  bool mode1;
+  int prec;
+  DType out;
+};
+
+int launch_jobs(ModeJobs& J, const LaunchKind& k, hipStream_t s) {
+  if (k.prec == SETD_PREC_F64) return k.mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
+  return k.mode1 ? launch_mode1_lp(J, k.prec, k.out, s) : launch_modeB_lp(J, k.prec, k.out, s);
+}
+
+int flush(ModeJobs& J, const LaunchKind& k, hipStream_t s) {
   if (J.njobs == 0) return SETD_OK;
-  int rc = mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
+  int rc = launch_jobs(J, k, s);
   J.njobs = 0;
   return rc;
 }
 
-int push(ModeJobs& J, const ModeJob& jb, bool mode1, hipStream_t s) {
-  if (J.njobs == kMaxJobs) SETD_TRY(flush(J, mode1, s));
+int push(ModeJobs& J, const ModeJob& jb, const LaunchKind& k, hipStream_t s) {
+  if (J.njobs == kMaxJobs) SETD_TRY(flush(J, k, s));
   J.job[J.njobs++] = jb;
   return SETD_OK;
 }
 
+// Packs a matrix for the mode kernels of the given arithmetic: mode 1 reads
+// it row-major; modes >= 2 column-major (FP64, FP32) or row-major (bf16).
+int pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s) {
+  if (prec == SETD_PREC_F64) return pack_matrix_f64(M, n, scale, mu == 0, (double*)out, s);
+  if (prec == SETD_PREC_F32) return pack_matrix_f32(M, n, scale, mu == 0, (float*)out, s);
+  return pack_matrix_bf16(M, n, scale, true, prec == SETD_PREC_BF16X3 ? 3 : 2, out, s);
+}
+
 // Runs all outputs of a group: d grouped launches (or more if a launch
-// would exceed kMaxJobs).  dims has d >= 2 entries.
-int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, hipStream_t s) {
+// would exceed kMaxJobs).  dims has d >= 2 entries.  With a reduced-precision
+// `prec`, term inputs and Y1/Y2 are FP32 and the outputs FP64.
+int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s) {
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) N *= dims[mu];
+  const DType mid = prec == SETD_PREC_F64 ? DType::F64 : DType::F32;
+  const LaunchKind k1{true, prec, mid}, kb{false, prec, mid}, klast{false, prec, DType::F64};
   ModeJobs J;
   J.njobs = 0;
   // mode 1 -> Y1
   for (int o = 0; o < nouts; ++o)
     for (int t = 0; t < outs[o].nterms; ++t) {
       const TuckerTerm& tm = outs[o].term[t];
-      SETD_TRY(push(J, mk_job(tm.X, tm.P[0], 1.0, tm.Y1, nullptr, 1, dims[0], N / dims[0]), true, s));
+      SETD_TRY(push(J, mk_job(tm.X, tm.P[0], 1.0, tm.Y1, nullptr, 1, dims[0], N / dims[0]), k1, s));
     }
-  SETD_TRY(flush(J, true, s));
+  SETD_TRY(flush(J, k1, s));
   // inner modes, ping-pong Y1 <-> Y2
   int64_t na = dims[0];
   for (int mu = 1; mu < d - 1; ++mu) {
@@ -206,11 +244,11 @@ int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, hipStre
     for (int o = 0; o < nouts; ++o)
       for (int t = 0; t < outs[o].nterms; ++t) {
         const TuckerTerm& tm = outs[o].term[t];
-        const double* src = (mu % 2 == 1) ? tm.Y1 : tm.Y2;
-        double* dst = (mu % 2 == 1) ? tm.Y2 : tm.Y1;
-        SETD_TRY(push(J, mk_job(src, tm.P[mu], 1.0, dst, nullptr, na, dims[mu], nb), false, s));
+        const void* src = (mu % 2 == 1) ? tm.Y1 : tm.Y2;
+        void* dst = (mu % 2 == 1) ? tm.Y2 : tm.Y1;
+        SETD_TRY(push(J, mk_job(src, tm.P[mu], 1.0, dst, nullptr, na, dims[mu], nb), kb, s));
       }
-    SETD_TRY(flush(J, false, s));
+    SETD_TRY(flush(J, kb, s));
     na *= dims[mu];
   }
   // last mode: terms summed along the contraction, base added
@@ -230,9 +268,9 @@ int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, hipStre
     jb.nb = 1;
     jb.n = dims[mu];
     jb.ldp = packed_ld(dims[mu]);
-    SETD_TRY(push(J, jb, false, s));
+    SETD_TRY(push(J, jb, klast, s));
   }
-  return flush(J, false, s);
+  return flush(J, klast, s);
 }
 
 bool is_tridiagonal(const std::vector<double>& A, int n) {
@@ -267,23 +305,24 @@ int build_bank(setd_ctx* c, hipStream_t s) {
     return (const double*)q;
   };
 
-  // packed bank + packed A
+  // packed bank (in the context's arithmetic) + packed A (FP64, dense K path)
   size_t bbytes = 0;
   for (int cc = 0; cc < c->ncomp; ++cc)
-    for (int mu = 0; mu < d; ++mu) bbytes += (5 * c->nterms + 1) * packed_bytes(c->dims[mu], SETD_PREC_F64);
+    for (int mu = 0; mu < d; ++mu)
+      bbytes += 5 * c->nterms * packed_bytes(c->dims[mu], c->prec) + packed_bytes(c->dims[mu], SETD_PREC_F64);
   SETD_TRY(c->bank_mem.alloc(bbytes));
   {
     char* q = (char*)c->bank_mem.p;
     for (int cc = 0; cc < c->ncomp; ++cc)
       for (int mu = 0; mu < d; ++mu) {
-        const size_t pb = packed_bytes(c->dims[mu], SETD_PREC_F64);
+        const size_t pb = packed_bytes(c->dims[mu], c->prec);
         for (int e = 0; e < 5; ++e)
           for (int t = 0; t < c->nterms; ++t) {
             c->bank[cc][e][t][mu] = q;
             q += pb;
           }
         c->Apk[cc][mu] = q;
-        q += pb;
+        q += packed_bytes(c->dims[mu], SETD_PREC_F64);
       }
   }
 
@@ -319,14 +358,12 @@ int build_bank(setd_ctx* c, hipStream_t s) {
         SETD_TRY(phi_batch(Adev(cc, mu), n, scal[mu].data(), E, 2, outs.data(), s));
       }
       const double* src = (const double*)raw[rep[mu]].p;
-      const bool rowmajor = (mu == 0);
       for (int k = 0; k < E; ++k) {
         const int e = which[mu][k] / 3, t = which[mu][k] % 3;
         const int li = c->sp[kBankEll[e]].ell_i[t];
-        SETD_TRY(pack_matrix_f64(src + ((size_t)k * 3 + li) * nn, n, 1.0, rowmajor, (double*)c->bank[cc][e][t][mu],
-                                 s));
+        SETD_TRY(pack_for(c->prec, src + ((size_t)k * 3 + li) * nn, n, 1.0, mu, c->bank[cc][e][t][mu], s));
       }
-      SETD_TRY(pack_matrix_f64(Adev(cc, mu), n, 1.0, rowmajor, (double*)c->Apk[cc][mu], s));
+      SETD_TRY(pack_matrix_f64(Adev(cc, mu), n, 1.0, mu == 0, (double*)c->Apk[cc][mu], s));
     }
     SETD_HIP(hipStreamSynchronize(s));   // raw buffers are released at scope exit
   }
@@ -372,13 +409,20 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
   const int d = c->d, nc = c->ncomp, T = c->nterms;
   const int64_t N = c->N;
   const double tau = c->tau;
-  // 1. G, F
+  const int prec = c->prec;
+  const bool lp = prec != SETD_PREC_F64;
+  const DType tdt = lp ? DType::F32 : DType::F64;   // type of F, D and the intermediates
+  const size_t es = lp ? 4 : 8;
+  auto Fc_ = [&](int cc) { return (void*)((char*)c->F + cc * N * es); };
+  auto Dc_ = [&](int cc) { return (void*)((char*)c->D + cc * N * es); };
+  // 1. G, F (F in the Tucker arithmetic's storage type; G stays FP64)
   if (c->tridiag) {
-    SETD_TRY(launch_gf_stencil(u, nc, N, d, c->dims, c->st, gp, c->G, c->F, DType::F64, s));
+    SETD_TRY(launch_gf_stencil(u, nc, N, d, c->dims, c->st, gp, c->G, c->F, tdt, s));
   } else {
     SETD_TRY(launch_g(u, nc, N, gp, c->G, s));
     for (int cc = 0; cc < nc; ++cc) {
-      double* Fc = c->F + cc * N;
+      // FP64 K action into F (or, reduced precision, into W then rounded)
+      double* Fc = lp ? c->W + cc * N : c->F + cc * N;
       const double* uc = u + cc * N;
       ModeJobs J;
       J.njobs = 1;
@@ -391,6 +435,7 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
         SETD_TRY(launch_modeB_f64(J, s));
         na *= c->dims[mu];
       }
+      if (lp) SETD_TRY(launch_copy_convert(Fc, Fc_(cc), N, DType::F32, s));
     }
   }
   const int e21 = bank_index(SETD_STAGE_2, 1), e31 = bank_index(SETD_STAGE_3, 1), e32 = bank_index(SETD_STAGE_3, 2),
@@ -413,14 +458,14 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
         o.base = u + cc * N;
         o.nterms = T;
         for (int t = 0; t < T; ++t)
-          o.term[t] = {c->F + cc * N, c->bank[cc][tg[k].e][t], tg[k].mult * S1.eta[t], c->Y1[cc][k * T + t],
+          o.term[t] = {Fc_(cc), c->bank[cc][tg[k].e][t], tg[k].mult * S1.eta[t], c->Y1[cc][k * T + t],
                        c->Y2[cc][k * T + t]};
       }
     }
-    SETD_TRY(run_tucker_group(d, c->dims, outs, no, s));
+    SETD_TRY(run_tucker_group(d, c->dims, outs, no, prec, s));
   }
   // 3. D = g(U2) - G
-  SETD_TRY(launch_stage_d(c->U2, c->G, nc, N, gp, c->D, DType::F64, s));
+  SETD_TRY(launch_stage_d(c->U2, c->G, nc, N, gp, c->D, tdt, s));
   // 4. U3 += 4tau/3 S_2(2tau/3) D
   {
     TuckerOut outs[2];
@@ -430,12 +475,12 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
       o.base = c->U3 + cc * N;
       o.nterms = T;
       for (int t = 0; t < T; ++t)
-        o.term[t] = {c->D + cc * N, c->bank[cc][e32][t], 4.0 * tau / 3.0 * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
+        o.term[t] = {Dc_(cc), c->bank[cc][e32][t], 4.0 * tau / 3.0 * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
-    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, s));
+    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s));
   }
   // 5. D = g(U3) - G
-  SETD_TRY(launch_stage_d(c->U3, c->G, nc, N, gp, c->D, DType::F64, s));
+  SETD_TRY(launch_stage_d(c->U3, c->G, nc, N, gp, c->D, tdt, s));
   // 6. U = W + 3tau/2 S_2(tau) D
   {
     TuckerOut outs[2];
@@ -445,10 +490,56 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
       o.base = c->W + cc * N;
       o.nterms = T;
       for (int t = 0; t < T; ++t)
-        o.term[t] = {c->D + cc * N, c->bank[cc][ef2][t], 1.5 * tau * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
+        o.term[t] = {Dc_(cc), c->bank[cc][ef2][t], 1.5 * tau * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
-    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, s));
+    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s));
   }
+  return SETD_OK;
+}
+
+// Graph replay of one step: used unless SETD_GRAPH=0 or the kernel timing is
+// on (its event records would be frozen into the graph).
+bool use_graph(const setd_ctx* c) {
+  (void)c;
+  const char* e = std::getenv("SETD_GRAPH");
+  if (e && e[0] == '0') return false;
+  return !prof_on();
+}
+
+void drop_graph(setd_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->g_u = nullptr;
+}
+
+// Captures one step (kernels only; no memset or memcpy nodes) on the
+// context's own stream.
+int capture_step(setd_ctx* c, double* u, const GParams& gp) {
+  drop_graph(c);
+  if (!c->gstream) SETD_HIP(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+  if (!c->ev_in) SETD_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+  if (!c->ev_out) SETD_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  SETD_HIP(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+  const int rc = step_once(c, u, gp, c->gstream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->gstream, &graph);
+  if (rc != SETD_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess || !graph) {
+    set_error("step capture failed: %s", hipGetErrorString(e));
+    return SETD_EHIP;
+  }
+  const hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    c->gexec = nullptr;
+    set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+    return SETD_EHIP;
+  }
+  c->g_u = u;
+  c->g_gp = gp;
   return SETD_OK;
 }
 
@@ -532,10 +623,12 @@ size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec) {
   for (int mu = 0; mu < d; ++mu) {
     if (dims[mu] < 1 || dims[mu] > 4096) return 0;
     N *= dims[mu];
-    pk += round_up(packed_bytes((int)dims[mu], SETD_PREC_F64), 256);
+    pk += round_up(packed_bytes((int)dims[mu], prec), 256);
   }
-  (void)prec;
-  return pk + 2 * round_up(N * (int64_t)sizeof(double), 256) + 256;
+  if (!is_prec(prec)) return 0;
+  // two ping-pong intermediates, plus the FP32 copy of V for reduced precision
+  const int nbuf = prec == SETD_PREC_F64 ? 2 : 3;
+  return pk + nbuf * round_up(N * (int64_t)sizeof(double), 256) + 256;
 }
 
 int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, const double* const* M, double alpha,
@@ -550,7 +643,7 @@ int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, co
     N *= dims[mu];
   }
   SETD_CHECK_ARG(!overlap(V, N * 8, W, N * 8), "V and W overlap");
-  SETD_CHECK_ARG(prec == SETD_PREC_F64, "only SETD_PREC_F64 is implemented for setd_tucker_apply");
+  SETD_CHECK_ARG(is_prec(prec), "bad prec %d", prec);
   if (!std::isfinite(alpha) || !std::isfinite(beta)) {
     set_error("alpha/beta not finite");
     return SETD_ENONFINITE;
@@ -577,30 +670,38 @@ int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, co
     SETD_HIP(hipMallocAsync(&wsp, need, s));
     own = true;
   }
+  const bool lp = prec != SETD_PREC_F64;
+  const int64_t fb = round_up(N * 8, 256);
   char* q = (char*)round_up((int64_t)(uintptr_t)wsp, 256);
-  double* buf[2] = {(double*)q, (double*)(q + round_up(N * 8, 256))};
-  q += 2 * round_up(N * 8, 256);
+  void* buf[3] = {q, q + fb, q + 2 * fb};
+  q += (lp ? 3 : 2) * fb;
   void* P[8] = {};
   int rc = SETD_OK;
   for (int k = 0; k < nm && rc == SETD_OK; ++k) {
     const int mu = modes[k];
     P[mu] = q;
-    q += round_up(packed_bytes((int)dims[mu], SETD_PREC_F64), 256);
+    q += round_up(packed_bytes((int)dims[mu], prec), 256);
     const bool last = (k == nm - 1);
-    rc = pack_matrix_f64(M[mu], (int)dims[mu], last ? alpha : 1.0, mu == 0, (double*)P[mu], s);
+    rc = pack_for(prec, M[mu], (int)dims[mu], last ? alpha : 1.0, mu, P[mu], s);
   }
-  const double* src = V;
+  // reduced precision: the FP64 input is rounded to FP32 once
+  const void* src = V;
+  if (lp && rc == SETD_OK) {
+    rc = launch_copy_convert(V, buf[2], N, DType::F32, s);
+    src = buf[2];
+  }
   for (int k = 0; k < nm && rc == SETD_OK; ++k) {
     const int mu = modes[k];
     const bool last = (k == nm - 1);
-    double* dst = last ? W : buf[k & 1];
+    void* dst = last ? (void*)W : buf[k & 1];
     int64_t na = 1, nb = 1;
     for (int nu = 0; nu < mu; ++nu) na *= dims[nu];
     for (int nu = mu + 1; nu < d; ++nu) nb *= dims[nu];
     ModeJobs J;
     J.njobs = 1;
     J.job[0] = mk_job(src, P[mu], 1.0, dst, last ? base : nullptr, na, (int)dims[mu], nb);
-    rc = (mu == 0) ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
+    const LaunchKind kind{mu == 0, prec, (last || !lp) ? DType::F64 : DType::F32};
+    rc = launch_jobs(J, kind, s);
     src = dst;
   }
   if (own) {
@@ -626,11 +727,7 @@ int setd_ctx_create(setd_ctx** out, int d, const int64_t* dims, int ncomp, const
     set_error("tau is not finite");
     return SETD_ENONFINITE;
   }
-  SETD_CHECK_ARG(prec == SETD_PREC_F64 || prec == SETD_PREC_F32 || prec == SETD_PREC_BF16X3, "bad prec %d", prec);
-  if (prec != SETD_PREC_F64) {
-    set_error("reduced-precision contexts are not built in this library version");
-    return SETD_EUNSUPPORTED;
-  }
+  SETD_CHECK_ARG(is_prec(prec), "bad prec %d", prec);
   for (int mu = 0; mu < d; ++mu)
     SETD_CHECK_ARG(dims[mu] >= 2 && dims[mu] <= 1024, "dims[%d] = %lld outside 2..1024", mu, (long long)dims[mu]);
   for (int k = 0; k < ncomp * d; ++k) SETD_CHECK_ARG(A[k] != nullptr, "A[%d] is NULL", k);
@@ -717,9 +814,9 @@ int setd_ctx_create(setd_ctx** out, int d, const int64_t* dims, int ncomp, const
   {
     const int T = c->nterms;
     const int ny = 3 * T;
-    const int64_t fields = 6 * (int64_t)ncomp + (int64_t)ncomp * ny * (d == 3 ? 2 : 1);
+    const int64_t fields = 6 * (int64_t)ncomp + (int64_t)ncomp * ny * (d == 3 ? 2 : 1) + 1;
     const size_t fb = round_up(c->N * 8, 256);
-    if ((rc = c->work_mem.alloc(fields * fb + norm_workspace_bytes() + 256)) != SETD_OK) return fail(rc);
+    if ((rc = c->work_mem.alloc(fields * fb + 256)) != SETD_OK) return fail(rc);
     char* q = (char*)c->work_mem.p;
     auto take = [&](int64_t nf) {
       double* p = (double*)q;
@@ -739,7 +836,7 @@ int setd_ctx_create(setd_ctx** out, int d, const int64_t* dims, int ncomp, const
         if (d == 3) c->Y2[cc][k] = take(1);
         else c->Y2[cc][k] = nullptr;
       }
-    c->norm_ws = (double*)q;
+    c->aux = take(1);
   }
   if ((rc = build_bank(c, s)) != SETD_OK) return fail(rc);
   *out = c;
@@ -776,12 +873,18 @@ int setd_split_phi_apply(setd_ctx* c, int comp, int ell, int stage, const double
     base = W;
   }
   const Splitting& S = c->sp[ell];
+  const void* src = V;
+  if (c->prec != SETD_PREC_F64) {   // reduced precision: round the input to FP32 once
+    SETD_TRY(launch_copy_convert(V, c->aux, c->N, DType::F32, s));
+    src = c->aux;
+  }
   TuckerOut o;
   o.Y = W;
   o.base = base;
   o.nterms = S.nterms;
-  for (int t = 0; t < S.nterms; ++t) o.term[t] = {V, c->bank[comp][e][t], scale * S.eta[t], c->Y1[0][t], c->Y2[0][t]};
-  return run_tucker_group(c->d, c->dims, &o, 1, s);
+  for (int t = 0; t < S.nterms; ++t)
+    o.term[t] = {src, c->bank[comp][e][t], scale * S.eta[t], c->Y1[0][t], c->Y2[0][t]};
+  return run_tucker_group(c->d, c->dims, &o, 1, c->prec, s);
 }
 
 int setd_etd_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params, int nparams,
@@ -801,6 +904,24 @@ int setd_etd_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, co
   if (tau != c->tau) {
     c->tau = tau;
     SETD_TRY(build_bank(c, s));
+    drop_graph(c);
+  }
+  if (nsteps == 0) return SETD_OK;
+  if (use_graph(c)) {
+    int rc = SETD_OK;
+    bool same = c->gexec && c->g_u == u && c->g_gp.kind == gp.kind;
+    for (int k = 0; k < 4; ++k) same = same && c->g_gp.p[k] == gp.p[k];
+    if (!same) rc = capture_step(c, u, gp);
+    if (rc == SETD_OK) {
+      SETD_HIP(hipEventRecord(c->ev_in, s));
+      SETD_HIP(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+      for (int k = 0; k < nsteps; ++k) SETD_HIP(hipGraphLaunch(c->gexec, c->gstream));
+      SETD_HIP(hipEventRecord(c->ev_out, c->gstream));
+      SETD_HIP(hipStreamWaitEvent(s, c->ev_out, 0));
+      return SETD_OK;
+    }
+    drop_graph(c);   // capture failed: fall back to direct launches
+    clear_error();
   }
   for (int k = 0; k < nsteps; ++k) SETD_TRY(step_once(c, u, gp, s));
   return SETD_OK;
