@@ -46,6 +46,52 @@ def mode_flops_per_step(dims, nterms, ncomp=2):
     return ncomp * 5 * nterms * per_tucker
 
 
+KERNEL_SOURCES = {"mode1_f64": "paper_2310_07551_amd/csrc/mode_f64.hip",
+                  "modeB_f64": "paper_2310_07551_amd/csrc/mode_f64.hip",
+                  "mode1_lp": "paper_2310_07551_amd/csrc/mode_lp.hip",
+                  "modeB_lp": "paper_2310_07551_amd/csrc/mode_lp.hip",
+                  "pointwise": "paper_2310_07551_amd/csrc/pointwise.hip"}
+
+
+def source_sha1(kernel):
+    import hashlib
+    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()
+
+
+def counted_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/traffic_<kernel>_<workload>.txt (FETCH_SIZE + WRITE_SIZE per
+    dispatch, scaled by the same counters on a copy of known size); None when
+    there is no summary or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha1") != source_sha1(kernel):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mbytes, reps=5):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    import torch
+    n = int(mbytes * 1e6) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copy probe: %d launches of a %d-byte read + %d-byte write" % (reps, n * 8, n * 8))
+
+
 def cpu_baseline(prob, nsteps):
     import numpy as np
     import oracle
@@ -73,6 +119,8 @@ def main():
     ap.add_argument("--workload", default="fhn3d_256")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB",
+                    help="only run a plain device copy of this size (HBM counter calibration) and exit")
     ap.add_argument("--forms", default="f64,f32,bf16x3,bf16x2",
                     help="arithmetic forms to time (f64 always runs; f32, bf16x3, bf16x2 are compared against it)")
     args = ap.parse_args()
@@ -82,6 +130,10 @@ def main():
         print("bench.py measures one GPU: the split-ETD3 path here runs on a single MI355X "
               "(no multi-GPU path is built); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
     import paper_2310_07551_amd as setd
@@ -153,6 +205,8 @@ def main():
         achieved = dp["bytes"] / (dp["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None)
+    tb = counted_traffic(dom, args.workload)
+    roof["traffic"] = None if tb is None else round(tb, 0)
     roof["kernel"] = dom
     roof["launches"] = dp["launches"]
     roof["avg_launch_ms"] = round(dp["ms"] / max(1, dp["launches"]), 4)

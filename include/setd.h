@@ -173,6 +173,17 @@ int setd_etd_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
                   const double* params, int nparams, void* stream);
 
 /*
+ * Second-order split integrator etd2rkds (the paper's comparison method,
+ * Section 1): eq. ETD2RK
+ *     u2 = u + tau phi_1(tau K) f(u),  u_new = u2 + tau phi_2(tau K)(g(u2) - g(u)),
+ * with phi_l(tau K) v replaced by the second-order splitting eq. secondord,
+ * l!^(d-1) T(V, {phi_l(tau A_mu)}): one Tucker operator per phi action.
+ * Same context, arguments and in-place semantics as setd_etd_step.
+ */
+int setd_etd2_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
+                   const double* params, int nparams, void* stream);
+
+/*
  * Norms for error reporting (deterministic fixed-order reductions):
  *   out[0] = ||x||_2, out[1] = ||x||_inf, and when y != NULL
  *   out[2] = ||x - y||_2, out[3] = ||x - y||_inf   (out is host, 4 doubles).

@@ -19,7 +19,7 @@ special cases, observed convergence orders); see those tests for the list.
 """
 from .coeffs import split_coefficients, table1_real, table3_real
 from .etd import (BANK_ENTRIES, G_FHN, G_NONE, G_SCHNAKENBERG, STAGE_SCALE, PhiBank, etd_step, integrate,
-                  make_banks, reaction, split2_apply)
+                  make_banks, reaction, split2_apply, Phi2Bank, etd2rkds_step, integrate_etd2rkds)
 from .norms import rel_inf, rel_l2
 from .phi import phi, phi_all
 from .tensor import kron_sum_action, mode_product, tucker
@@ -27,5 +27,6 @@ from .tensor import kron_sum_action, mode_product, tucker
 __all__ = [
     "split_coefficients", "table1_real", "table3_real", "BANK_ENTRIES", "G_FHN", "G_NONE", "G_SCHNAKENBERG",
     "STAGE_SCALE", "PhiBank", "etd_step", "integrate", "make_banks", "reaction", "split2_apply",
+    "Phi2Bank", "etd2rkds_step", "integrate_etd2rkds",
     "rel_inf", "rel_l2", "phi", "phi_all", "kron_sum_action", "mode_product", "tucker",
 ]

@@ -126,3 +126,37 @@ def split2_apply(As: Sequence[np.ndarray], ctau: float, ell: int, V: np.ndarray)
     d = len(As)
     fact = float(np.prod(np.arange(1, ell + 1))) ** (d - 1)
     return fact * tucker(V, [phi(ctau * A, ell) for A in As])
+
+
+class Phi2Bank:
+    """phi_1(tau A_mu) and phi_2(tau A_mu) for the second-order split integrator."""
+
+    def __init__(self, As: Sequence[np.ndarray], tau: float):
+        self.d = len(As)
+        self.mats = {ell: [phi(tau * A, ell) for A in As] for ell in (1, 2)}
+
+    def apply(self, ell: int, V: np.ndarray) -> np.ndarray:
+        """eq. (secondord) at c = 1: l!^(d-1) T(V, {phi_l(tau A_mu)})."""
+        fact = float(np.prod(np.arange(1, ell + 1))) ** (self.d - 1)
+        return fact * tucker(V, self.mats[ell])
+
+
+def etd2rkds_step(U: Sequence[np.ndarray], As: Sequence[Sequence[np.ndarray]], banks: Sequence[Phi2Bank],
+                  tau: float, kind: int, params: Sequence[float]) -> List[np.ndarray]:
+    """One step of etd2rkds: eq. (ETD2RK),
+        u2 = u + tau phi_1(tau K) f(u),  u_new = u2 + tau phi_2(tau K)(g(u2) - g(u)),
+    with both phi actions replaced by eq. (secondord)."""
+    nc = len(U)
+    G = reaction(kind, U, params)
+    F = [kron_sum_action(U[c], As[c]) + G[c] for c in range(nc)]
+    U2 = [U[c] + tau * banks[c].apply(1, F[c]) for c in range(nc)]
+    G2 = reaction(kind, U2, params)
+    return [U2[c] + tau * banks[c].apply(2, G2[c] - G[c]) for c in range(nc)]
+
+
+def integrate_etd2rkds(U0, As, tau: float, nsteps: int, kind: int, params) -> List[np.ndarray]:
+    banks = [Phi2Bank(Ac, tau) for Ac in As]
+    U = [np.array(x, dtype=np.float64, order="F") for x in U0]
+    for _ in range(nsteps):
+        U = etd2rkds_step(U, As, banks, tau, kind, params)
+    return U

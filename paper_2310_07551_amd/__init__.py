@@ -190,3 +190,16 @@ class Context:
                                              _stream(stream)))
         self.tau = t
         return u
+
+    def step2(self, u, nsteps: int, g_kind: int, params: Sequence[float], tau: Optional[float] = None,
+              stream=None):
+        """Advance u by nsteps steps of the second-order split integrator etd2rkds, in place."""
+        _check_dev(u, "u")
+        if u.numel() != self.ncomp * self.N:
+            raise ValueError("u must hold ncomp*N values")
+        p = (ctypes.c_double * max(1, len(params)))(*[float(x) for x in params])
+        t = self.tau if tau is None else float(tau)
+        _lib.check(_lib.load().setd_etd2_step(self._h, u.data_ptr(), int(nsteps), t, int(g_kind), p, len(params),
+                                              _stream(stream)))
+        self.tau = t
+        return u

@@ -46,8 +46,11 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // ---------------------------------------------------------------------------
 // mode 1
 // ---------------------------------------------------------------------------
-template <int TM, int TN, bool VEC>
+template <int TM, int TN, int MODE>
 __global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+  // MODE 0: element loads with bounds checks everywhere; 1: vector loads
+  // (aligned operands); 2: additionally every tile interior and n % 32 == 0.
+  constexpr bool VEC = MODE >= 1;
   const int64_t t = remap_xcd(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const ModeJob& jb = J.job[find_job(J, t)];
@@ -82,39 +85,65 @@ __global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
 
-  d4 a[TM], bx[TN];
-  auto load = [&](int p0, d4* ar, d4* br) {
-#pragma unroll
-    for (int m = 0; m < TM; ++m) ar[m] = *(const d4*)(pa[m] + p0) * sc;
-    const bool full = VEC && (p0 + 16 <= n);
-#pragma unroll
-    for (int u = 0; u < TN; ++u) {
-      if (full) {
-        br[u] = vb[u] ? *(const d4*)(pb[u] + p0) : d4{0.0, 0.0, 0.0, 0.0};
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] : 0.0;
-      }
-    }
-  };
-
-  load(0, a, bx);
-  for (int p0 = 0; p0 < n; p0 += 16) {
-    d4 an[TM], bn[TN];
-    const bool more = p0 + 16 < n;
-    if (more) load(p0 + 16, an, bn);
+  // The scale multiplies the operand where it is used, never inside a load:
+  // a multiply right after a prefetch would make the wave wait for it.
+  auto mma = [&](const d4* ar, const d4* br) {
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-      for (int m = 0; m < TM; ++m)
+      for (int m = 0; m < TM; ++m) {
+        const double av = ar[m][jj] * sc;
 #pragma unroll
-        for (int u = 0; u < TN; ++u) acc[m][u] = mfma(a[m][jj], bx[u][jj], acc[m][u]);
-    if (more) {
+        for (int u = 0; u < TN; ++u) acc[m][u] = mfma(av, br[u][jj], acc[m][u]);
+      }
+  };
+  if constexpr (MODE == 2) {
+    // Interior tile: two k-chunks per iteration in ping-pong registers, no
+    // masks and no register copies.  The last iteration re-reads a valid
+    // chunk instead of branching.
+    auto load = [&](int p0, d4* ar, d4* br) {
 #pragma unroll
-      for (int m = 0; m < TM; ++m) a[m] = an[m];
+      for (int m = 0; m < TM; ++m) ar[m] = *(const d4*)(pa[m] + p0);
 #pragma unroll
-      for (int u = 0; u < TN; ++u) bx[u] = bn[u];
+      for (int u = 0; u < TN; ++u) br[u] = *(const d4*)(pb[u] + p0);
+    };
+    d4 a0[TM], b0r[TN], a1[TM], b1r[TN];
+    load(0, a0, b0r);
+    for (int p0 = 0; p0 < n; p0 += 32) {
+      load(p0 + 16, a1, b1r);
+      mma(a0, b0r);
+      load(p0 + 32 < n ? p0 + 32 : p0, a0, b0r);
+      mma(a1, b1r);
+    }
+  } else {
+    auto load = [&](int p0, d4* ar, d4* br) {
+#pragma unroll
+      for (int m = 0; m < TM; ++m) ar[m] = *(const d4*)(pa[m] + p0);
+      const bool full = VEC && (p0 + 16 <= n);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) {
+        if (full) {
+          br[u] = vb[u] ? *(const d4*)(pb[u] + p0) : d4{0.0, 0.0, 0.0, 0.0};
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] : 0.0;
+        }
+      }
+    };
+    d4 a[TM], bx[TN];
+    load(0, a, bx);
+    for (int p0 = 0; p0 < n; p0 += 16) {
+      d4 an[TM], bn[TN];
+      const bool more = p0 + 16 < n;
+      if (more) load(p0 + 16, an, bn);
+      mma(a, bx);
+      if (more) {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) a[m] = an[m];
+#pragma unroll
+        for (int u = 0; u < TN; ++u) bx[u] = bn[u];
+      }
     }
   }
 
@@ -155,8 +184,9 @@ __global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t
 // ---------------------------------------------------------------------------
 // modes >= 2
 // ---------------------------------------------------------------------------
-template <int TM, int TN, bool VEC>
+template <int TM, int TN, int MODE>
 __global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+  constexpr bool VEC = MODE >= 1;   // as in the mode-1 kernel
   const int64_t t = remap_xcd(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const ModeJob& jb = J.job[find_job(J, t)];
@@ -181,10 +211,61 @@ __global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t
     for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int64_t slab = na * (int64_t)n * b;
+  constexpr bool fast = MODE == 2;   // every tile interior, n % 32 == 0 (checked at launch)
   for (int term = 0; term < nterms; ++term) {
     const double* __restrict__ xb = (const double*)jb.X[term] + slab + arow + na * g;
     const double* __restrict__ pbp = (const double*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
     const double sc = jb.scale[term];
+
+    if constexpr (fast) {
+      // Interior tile: blocks of KB k-steps (4 KB values of p) in ping-pong
+      // registers; the scale is applied to the matrix operand at use.
+      constexpr int KB = 4;
+      auto loadblk = [&](int p0, double (*xr)[TM], double (*pr)[TN]) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          const double* xs = xb + na * (int64_t)(p0 + 4 * k);
+          if constexpr (TM == 4) {
+            const d4 v = *(const d4*)xs;
+#pragma unroll
+            for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+          } else {
+            const d2 v = *(const d2*)xs;
+#pragma unroll
+            for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+          }
+          const double* ps = pbp + (int64_t)ldp * (p0 + 4 * k);
+          if constexpr (TN == 4) {
+            const d4 v = *(const d4*)ps;
+#pragma unroll
+            for (int u = 0; u < TN; ++u) pr[k][u] = v[u];
+          } else {
+            const d2 v = *(const d2*)ps;
+#pragma unroll
+            for (int u = 0; u < TN; ++u) pr[k][u] = v[u];
+          }
+        }
+      };
+      auto mmablk = [&](double (*xr)[TM], double (*pr)[TN]) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+          for (int u = 0; u < TN; ++u) {
+            const double pv = pr[k][u] * sc;
+#pragma unroll
+            for (int m = 0; m < TM; ++m) acc[m][u] = mfma(xr[k][m], pv, acc[m][u]);
+          }
+      };
+      double xa[KB][TM], pa[KB][TN], xq[KB][TM], pq[KB][TN];
+      loadblk(0, xa, pa);
+      for (int p0 = 0; p0 < n; p0 += 8 * KB) {
+        loadblk(p0 + 4 * KB, xq, pq);
+        mmablk(xa, pa);
+        loadblk(p0 + 8 * KB < n ? p0 + 8 * KB : p0, xa, pa);
+        mmablk(xq, pq);
+      }
+      continue;
+    }
 
     auto load = [&](int p0, double* xr, double* pr) {
       const bool vp = p0 + g < n;
@@ -203,16 +284,16 @@ __global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t
       }
       const double* ps = pbp + (int64_t)ldp * p0;
       if (TN == 4) {
-        const d4 v = *(const d4*)ps * sc;
+        const d4 v = *(const d4*)ps;
 #pragma unroll
         for (int u = 0; u < TN; ++u) pr[u] = v[u];
       } else if (TN == 2) {
-        const d2 v = *(const d2*)ps * sc;
+        const d2 v = *(const d2*)ps;
 #pragma unroll
         for (int u = 0; u < TN; ++u) pr[u] = v[u];
       } else {
 #pragma unroll
-        for (int u = 0; u < TN; ++u) pr[u] = ps[u] * sc;
+        for (int u = 0; u < TN; ++u) pr[u] = ps[u];
       }
     };
 
@@ -223,9 +304,11 @@ __global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t
       const bool more = p0 + 4 < n;
       if (more) load(p0 + 4, xn, pn);
 #pragma unroll
-      for (int m = 0; m < TM; ++m)
+      for (int u = 0; u < TN; ++u) {
+        const double pv = pr[u] * sc;
 #pragma unroll
-        for (int u = 0; u < TN; ++u) acc[m][u] = mfma(xr[m], pr[u], acc[m][u]);
+        for (int m = 0; m < TM; ++m) acc[m][u] = mfma(xr[m], pv, acc[m][u]);
+      }
       if (more) {
 #pragma unroll
         for (int m = 0; m < TM; ++m) xr[m] = xn[m];
@@ -311,24 +394,16 @@ int finish_tiles(ModeJobs& J, bool mode1, int TM, int TN) {
 
 }  // namespace
 
-#define SETD_MODE1_CASE(TM_, TN_)                                                           \
-  if (cfg.tm == TM_ && cfg.tn == TN_) {                                                     \
-    if (vec)                                                                                \
-      hipLaunchKernelGGL((mode1_f64_kernel<TM_, TN_, true>), grid, dim3(64), 0, s, J, per); \
-    else                                                                                    \
-      hipLaunchKernelGGL((mode1_f64_kernel<TM_, TN_, false>), grid, dim3(64), 0, s, J, per);\
-    SETD_LAUNCHED();                                                                        \
-    return SETD_OK;                                                                         \
-  }
-
-#define SETD_MODEB_CASE(TM_, TN_)                                                           \
-  if (cfg.tm == TM_ && cfg.tn == TN_) {                                                     \
-    if (vec)                                                                                \
-      hipLaunchKernelGGL((modeB_f64_kernel<TM_, TN_, true>), grid, dim3(64), 0, s, J, per); \
-    else                                                                                    \
-      hipLaunchKernelGGL((modeB_f64_kernel<TM_, TN_, false>), grid, dim3(64), 0, s, J, per);\
-    SETD_LAUNCHED();                                                                        \
-    return SETD_OK;                                                                         \
+#define SETD_LAUNCH_MODES(KERNEL, TM_, TN_)                                                    \
+  if (cfg.tm == TM_ && cfg.tn == TN_) {                                                       \
+    if (mode == 2)                                                                            \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 2>), grid, dim3(64), 0, s, J, per);                 \
+    else if (mode == 1)                                                                       \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 1>), grid, dim3(64), 0, s, J, per);                 \
+    else                                                                                      \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 0>), grid, dim3(64), 0, s, J, per);                 \
+    SETD_LAUNCHED();                                                                          \
+    return SETD_OK;                                                                           \
   }
 
 void job_work(const ModeJobs& J, int es_in, int es_out, int es_mat, double& flops, double& bytes) {
@@ -354,12 +429,15 @@ int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
     const ModeJob& jb = J.job[j];
     vec = vec && (jb.n % 4 == 0) && aligned(jb.X[0], 32) && aligned(jb.Y, 16) && aligned(jb.base, 16);
   }
+  bool interior = vec && !std::getenv("SETD_NO_INTERIOR_PATH");
+  for (int j = 0; j < J.njobs; ++j) interior = interior && J.job[j].n % 32 == 0 && J.job[j].nb % (16 * cfg.tn) == 0;
+  const int mode = interior ? 2 : (vec ? 1 : 0);
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
-  SETD_MODE1_CASE(4, 4)
-  SETD_MODE1_CASE(4, 2)
-  SETD_MODE1_CASE(2, 4)
-  SETD_MODE1_CASE(2, 2)
+  SETD_LAUNCH_MODES(mode1_f64_kernel, 4, 4)
+  SETD_LAUNCH_MODES(mode1_f64_kernel, 4, 2)
+  SETD_LAUNCH_MODES(mode1_f64_kernel, 2, 4)
+  SETD_LAUNCH_MODES(mode1_f64_kernel, 2, 2)
   set_error("unsupported mode-1 tile");
   return SETD_EUNSUPPORTED;
 }
@@ -377,12 +455,15 @@ int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
     vec = vec && (jb.na % 4 == 0) && aligned(jb.Y, 16) && aligned(jb.base, 16);
     for (int t = 0; t < jb.nterms; ++t) vec = vec && aligned(jb.X[t], 32);
   }
+  bool interior = vec && !std::getenv("SETD_NO_INTERIOR_PATH");
+  for (int j = 0; j < J.njobs; ++j) interior = interior && J.job[j].n % 32 == 0 && J.job[j].na % (16 * cfg.tm) == 0;
+  const int mode = interior ? 2 : (vec ? 1 : 0);
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
-  SETD_MODEB_CASE(4, 4)
-  SETD_MODEB_CASE(4, 2)
-  SETD_MODEB_CASE(2, 4)
-  SETD_MODEB_CASE(2, 2)
+  SETD_LAUNCH_MODES(modeB_f64_kernel, 4, 4)
+  SETD_LAUNCH_MODES(modeB_f64_kernel, 4, 2)
+  SETD_LAUNCH_MODES(modeB_f64_kernel, 2, 4)
+  SETD_LAUNCH_MODES(modeB_f64_kernel, 2, 2)
   set_error("unsupported mode-b tile");
   return SETD_EUNSUPPORTED;
 }

@@ -133,6 +133,7 @@ struct setd_ctx {
   int nterms = 0;
   void* bank[2][5][3][3] = {};   // [comp][entry][term][mu] packed FP64 matrix
   void* Apk[2][3] = {};          // packed A for the dense K path
+  void* bank2[2][2][3] = {};     // [comp][ell-1][mu] phi_ell(tau A_mu) for etd2rkds
   double *G = nullptr, *F = nullptr, *U2 = nullptr, *U3 = nullptr, *W = nullptr, *D = nullptr;
   double* Y1[2][9] = {};
   double* Y2[2][9] = {};
@@ -144,6 +145,7 @@ struct setd_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   double* g_u = nullptr;
   GParams g_gp{};
+  const void* g_fn = nullptr;    // which step function the graph holds
   ~setd_ctx() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -309,7 +311,7 @@ int build_bank(setd_ctx* c, hipStream_t s) {
   size_t bbytes = 0;
   for (int cc = 0; cc < c->ncomp; ++cc)
     for (int mu = 0; mu < d; ++mu)
-      bbytes += 5 * c->nterms * packed_bytes(c->dims[mu], c->prec) + packed_bytes(c->dims[mu], SETD_PREC_F64);
+      bbytes += (5 * c->nterms + 2) * packed_bytes(c->dims[mu], c->prec) + packed_bytes(c->dims[mu], SETD_PREC_F64);
   SETD_TRY(c->bank_mem.alloc(bbytes));
   {
     char* q = (char*)c->bank_mem.p;
@@ -321,6 +323,10 @@ int build_bank(setd_ctx* c, hipStream_t s) {
             c->bank[cc][e][t][mu] = q;
             q += pb;
           }
+        for (int l = 0; l < 2; ++l) {
+          c->bank2[cc][l][mu] = q;
+          q += pb;
+        }
         c->Apk[cc][mu] = q;
         q += packed_bytes(c->dims[mu], SETD_PREC_F64);
       }
@@ -341,6 +347,8 @@ int build_bank(setd_ctx* c, hipStream_t s) {
           which[mu].push_back(e * 3 + t);
         }
       }
+      scal[mu].push_back(c->tau);   // phi_1, phi_2 (tau A_mu) of the second-order splitting
+      which[mu].push_back(-1);
       rep[mu] = mu;
       for (int nu = 0; nu < mu; ++nu)
         if (rep[nu] == nu && c->dims[nu] == c->dims[mu] && c->Ah[cc][nu] == c->Ah[cc][mu] &&
@@ -359,6 +367,11 @@ int build_bank(setd_ctx* c, hipStream_t s) {
       }
       const double* src = (const double*)raw[rep[mu]].p;
       for (int k = 0; k < E; ++k) {
+        if (which[mu][k] < 0) {
+          for (int l = 1; l <= 2; ++l)
+            SETD_TRY(pack_for(c->prec, src + ((size_t)k * 3 + l) * nn, n, 1.0, mu, c->bank2[cc][l - 1][mu], s));
+          continue;
+        }
         const int e = which[mu][k] / 3, t = which[mu][k] % 3;
         const int li = c->sp[kBankEll[e]].ell_i[t];
         SETD_TRY(pack_for(c->prec, src + ((size_t)k * 3 + li) * nn, n, 1.0, mu, c->bank[cc][e][t][mu], s));
@@ -405,17 +418,14 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 // Split phi action outputs for the F group: stage s, ell = 1.
-int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
-  const int d = c->d, nc = c->ncomp, T = c->nterms;
+// G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type.
+int compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+  const int d = c->d, nc = c->ncomp;
   const int64_t N = c->N;
-  const double tau = c->tau;
-  const int prec = c->prec;
-  const bool lp = prec != SETD_PREC_F64;
-  const DType tdt = lp ? DType::F32 : DType::F64;   // type of F, D and the intermediates
+  const bool lp = c->prec != SETD_PREC_F64;
+  const DType tdt = lp ? DType::F32 : DType::F64;
   const size_t es = lp ? 4 : 8;
   auto Fc_ = [&](int cc) { return (void*)((char*)c->F + cc * N * es); };
-  auto Dc_ = [&](int cc) { return (void*)((char*)c->D + cc * N * es); };
-  // 1. G, F (F in the Tucker arithmetic's storage type; G stays FP64)
   if (c->tridiag) {
     SETD_TRY(launch_gf_stencil(u, nc, N, d, c->dims, c->st, gp, c->G, c->F, tdt, s));
   } else {
@@ -438,6 +448,22 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
       if (lp) SETD_TRY(launch_copy_convert(Fc, Fc_(cc), N, DType::F32, s));
     }
   }
+  return SETD_OK;
+}
+
+// One exprk3ds_real step (the time loop of Algorithms 1 and 2).
+int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+  const int d = c->d, nc = c->ncomp, T = c->nterms;
+  const int64_t N = c->N;
+  const double tau = c->tau;
+  const int prec = c->prec;
+  const bool lp = prec != SETD_PREC_F64;
+  const DType tdt = lp ? DType::F32 : DType::F64;   // type of F, D and the intermediates
+  const size_t es = lp ? 4 : 8;
+  auto Fc_ = [&](int cc) { return (void*)((char*)c->F + cc * N * es); };
+  auto Dc_ = [&](int cc) { return (void*)((char*)c->D + cc * N * es); };
+  // 1. G, F
+  SETD_TRY(compute_gf(c, u, gp, s));
   const int e21 = bank_index(SETD_STAGE_2, 1), e31 = bank_index(SETD_STAGE_3, 1), e32 = bank_index(SETD_STAGE_3, 2),
             ef1 = bank_index(SETD_STAGE_F, 1), ef2 = bank_index(SETD_STAGE_F, 2);
   const Splitting& S1 = c->sp[1];
@@ -497,6 +523,38 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
   return SETD_OK;
 }
 
+// One etd2rkds step: U2 = U + tau T(F, {phi_1}), D = g(U2) - G,
+// U = U2 + tau 2^{d-1} T(D, {phi_2})  (eq. ETD2RK with eq. secondord).
+int step2_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+  const int d = c->d, nc = c->ncomp;
+  const int64_t N = c->N;
+  const bool lp = c->prec != SETD_PREC_F64;
+  const DType tdt = lp ? DType::F32 : DType::F64;
+  const size_t es = lp ? 4 : 8;
+  SETD_TRY(compute_gf(c, u, gp, s));
+  TuckerOut outs[2];
+  for (int cc = 0; cc < nc; ++cc) {
+    TuckerOut& o = outs[cc];
+    o.Y = c->U2 + cc * N;
+    o.base = u + cc * N;
+    o.nterms = 1;
+    o.term[0] = {(char*)c->F + cc * N * es, c->bank2[cc][0], c->tau, c->Y1[cc][0], c->Y2[cc][0]};
+  }
+  SETD_TRY(run_tucker_group(d, c->dims, outs, nc, c->prec, s));
+  SETD_TRY(launch_stage_d(c->U2, c->G, nc, N, gp, c->D, tdt, s));
+  const double fact = std::ldexp(1.0, d - 1);   // 2!^{d-1}
+  for (int cc = 0; cc < nc; ++cc) {
+    TuckerOut& o = outs[cc];
+    o.Y = u + cc * N;
+    o.base = c->U2 + cc * N;
+    o.nterms = 1;
+    o.term[0] = {(char*)c->D + cc * N * es, c->bank2[cc][1], c->tau * fact, c->Y1[cc][0], c->Y2[cc][0]};
+  }
+  return run_tucker_group(d, c->dims, outs, nc, c->prec, s);
+}
+
+typedef int (*StepFn)(setd_ctx*, double*, const GParams&, hipStream_t);
+
 // Graph replay of one step: used unless SETD_GRAPH=0 or the kernel timing is
 // on (its event records would be frozen into the graph).
 bool use_graph(const setd_ctx* c) {
@@ -514,13 +572,13 @@ void drop_graph(setd_ctx* c) {
 
 // Captures one step (kernels only; no memset or memcpy nodes) on the
 // context's own stream.
-int capture_step(setd_ctx* c, double* u, const GParams& gp) {
+int capture_step(setd_ctx* c, double* u, const GParams& gp, StepFn fn) {
   drop_graph(c);
   if (!c->gstream) SETD_HIP(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
   if (!c->ev_in) SETD_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   if (!c->ev_out) SETD_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
   SETD_HIP(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
-  const int rc = step_once(c, u, gp, c->gstream);
+  const int rc = fn(c, u, gp, c->gstream);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(c->gstream, &graph);
   if (rc != SETD_OK) {
@@ -540,6 +598,45 @@ int capture_step(setd_ctx* c, double* u, const GParams& gp) {
   }
   c->g_u = u;
   c->g_gp = gp;
+  c->g_fn = (const void*)fn;
+  return SETD_OK;
+}
+
+// nsteps applications of `fn` to u (graph replay when possible).
+int run_steps(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params, int nparams,
+              hipStream_t s, StepFn fn) {
+  SETD_CHECK_ARG(c != nullptr, "ctx is NULL");
+  SETD_CHECK_ARG(u != nullptr, "u is NULL");
+  SETD_CHECK_ARG(nsteps >= 0, "nsteps < 0");
+  SETD_CHECK_ARG(tau > 0.0, "tau must be positive");
+  if (!std::isfinite(tau)) {
+    set_error("tau is not finite");
+    return SETD_ENONFINITE;
+  }
+  GParams gp;
+  SETD_TRY(make_gparams(g_kind, params, nparams, c->ncomp, gp));
+  if (tau != c->tau) {
+    c->tau = tau;
+    SETD_TRY(build_bank(c, s));
+    drop_graph(c);
+  }
+  if (nsteps == 0) return SETD_OK;
+  if (use_graph(c)) {
+    bool same = c->gexec && c->g_u == u && c->g_fn == (const void*)fn && c->g_gp.kind == gp.kind;
+    for (int k = 0; k < 4; ++k) same = same && c->g_gp.p[k] == gp.p[k];
+    const int rc = same ? SETD_OK : capture_step(c, u, gp, fn);
+    if (rc == SETD_OK) {
+      SETD_HIP(hipEventRecord(c->ev_in, s));
+      SETD_HIP(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+      for (int k = 0; k < nsteps; ++k) SETD_HIP(hipGraphLaunch(c->gexec, c->gstream));
+      SETD_HIP(hipEventRecord(c->ev_out, c->gstream));
+      SETD_HIP(hipStreamWaitEvent(s, c->ev_out, 0));
+      return SETD_OK;
+    }
+    drop_graph(c);   // capture failed: fall back to direct launches
+    clear_error();
+  }
+  for (int k = 0; k < nsteps; ++k) SETD_TRY(fn(c, u, gp, s));
   return SETD_OK;
 }
 
@@ -890,41 +987,13 @@ int setd_split_phi_apply(setd_ctx* c, int comp, int ell, int stage, const double
 int setd_etd_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params, int nparams,
                   void* stream) {
   clear_error();
-  SETD_CHECK_ARG(c != nullptr, "ctx is NULL");
-  SETD_CHECK_ARG(u != nullptr, "u is NULL");
-  SETD_CHECK_ARG(nsteps >= 0, "nsteps < 0");
-  SETD_CHECK_ARG(tau > 0.0, "tau must be positive");
-  if (!std::isfinite(tau)) {
-    set_error("tau is not finite");
-    return SETD_ENONFINITE;
-  }
-  GParams gp;
-  SETD_TRY(make_gparams(g_kind, params, nparams, c->ncomp, gp));
-  hipStream_t s = (hipStream_t)stream;
-  if (tau != c->tau) {
-    c->tau = tau;
-    SETD_TRY(build_bank(c, s));
-    drop_graph(c);
-  }
-  if (nsteps == 0) return SETD_OK;
-  if (use_graph(c)) {
-    int rc = SETD_OK;
-    bool same = c->gexec && c->g_u == u && c->g_gp.kind == gp.kind;
-    for (int k = 0; k < 4; ++k) same = same && c->g_gp.p[k] == gp.p[k];
-    if (!same) rc = capture_step(c, u, gp);
-    if (rc == SETD_OK) {
-      SETD_HIP(hipEventRecord(c->ev_in, s));
-      SETD_HIP(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
-      for (int k = 0; k < nsteps; ++k) SETD_HIP(hipGraphLaunch(c->gexec, c->gstream));
-      SETD_HIP(hipEventRecord(c->ev_out, c->gstream));
-      SETD_HIP(hipStreamWaitEvent(s, c->ev_out, 0));
-      return SETD_OK;
-    }
-    drop_graph(c);   // capture failed: fall back to direct launches
-    clear_error();
-  }
-  for (int k = 0; k < nsteps; ++k) SETD_TRY(step_once(c, u, gp, s));
-  return SETD_OK;
+  return run_steps(c, u, nsteps, tau, g_kind, params, nparams, (hipStream_t)stream, step_once);
+}
+
+int setd_etd2_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params, int nparams,
+                   void* stream) {
+  clear_error();
+  return run_steps(c, u, nsteps, tau, g_kind, params, nparams, (hipStream_t)stream, step2_once);
 }
 
 int setd_field_norms(const double* x, const double* y, int64_t n, double* out, void* stream) {
