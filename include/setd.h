@@ -184,6 +184,72 @@ int setd_etd2_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
                    const double* params, int nparams, void* stream);
 
 /*
+ * Batched integration: nbatch independent instances of one kind of problem
+ * (same d, ncomp and tau; each with its own grid, matrices A_mu^(c) and
+ * reaction parameters) advanced together by split-ETD3 steps (the same step
+ * as setd_etd_step, applied to every instance; the paper's method is per
+ * instance, the batching is how the small instances fill the GPU).
+ * Every stage of a step is one launch over all instances: the mu-mode
+ * products of a Tucker group run from a work list of (instance, output,
+ * tile) entries walked by a persistent grid, the pointwise kernels over the
+ * points of all instances.  The step is captured in a hipGraph and replayed.
+ * Tile shapes and grid sizes are chosen by timing candidates on the batch's
+ * own work lists (setd_batch_tune; run automatically before the first step
+ * unless setd_batch_set_tiles chose them or SETD_BATCH_TUNE=0).
+ *
+ * setd_batch_create
+ *   nbatch  >= 1 instances.
+ *   d       2 or 3 (every instance).
+ *   dims    host array of nbatch*d sizes: dims[b*d + mu] = n_{mu+1} of
+ *           instance b, 2 <= n <= 1024 (grids may be non-square and differ
+ *           between instances).
+ *   ncomp   1 or 2.
+ *   A       host array of nbatch*ncomp*d device pointers: A[(b*ncomp + c)*d +
+ *           mu] is A_{mu+1}^(c) of instance b (column-major FP64).  Copied.
+ *   tau     step size shared by all instances, > 0.
+ *   prec    SETD_PREC_F64 only (others: SETD_EUNSUPPORTED).
+ *   Builds the phi bank of every instance (one phi build per distinct
+ *   matrix, scalars and packing; identical matrices are shared) and the work
+ *   buffers.  Synchronises `stream`.
+ *
+ * Layout of the batch state u (device, FP64, owned by the caller): instance
+ * b occupies elements off[b] .. off[b+1]-1 with component c of its grid
+ * (Fortran-ordered as everywhere in this header) at off[b] + c*cs[b], where
+ * cs[b] = N_b rounded up to a multiple of 8 (the gap, if any, is ignored).
+ * setd_batch_layout writes off (host, nbatch+1 entries; off[nbatch] = total
+ * length of u) and, if cs != NULL, cs (host, nbatch entries).
+ *
+ * setd_batch_step: nsteps steps of every instance, in place on u.
+ *   g_kind  SETD_G_* for every instance.
+ *   params  host array of nbatch*nparams values, instance b's at
+ *           params[b*nparams] (as for setd_etd_step); NULL if nparams = 0.
+ * The work lists refer to u itself: a call with another u rebuilds them
+ * (synchronising); calls that overlap on the same u race.
+ *
+ * setd_batch_tune times every candidate tile shape (2 or 4 tiles of 16 on
+ * each side) and grid cap on the phi_1 group of the step, separately for
+ * mode 1 and for modes >= 2, and keeps the fastest.  Synchronises `stream`.
+ * setd_batch_set_tiles fixes them instead: cfg (host) = {tm, tn, cap} for
+ * mode 1 followed by {tm, tn, cap} for modes >= 2 (cap = largest number of
+ * workgroups of a launch, 0 = one per tile).
+ * setd_batch_info (host, SETD_BATCH_INFO entries): the six tile values as
+ * for setd_batch_set_tiles, whether they were tuned or set, launches per
+ * step (0 before the first step), the length of u, and the number of
+ * distinct packed matrix sets.
+ */
+typedef struct setd_batch setd_batch;
+#define SETD_BATCH_INFO 10
+int setd_batch_create(setd_batch** batch, int nbatch, int d, const int64_t* dims, int ncomp,
+                      const double* const* A, double tau, int prec, void* stream);
+int setd_batch_destroy(setd_batch* batch);
+int setd_batch_layout(const setd_batch* batch, int64_t* off, int64_t* cs);
+int setd_batch_step(setd_batch* batch, double* u, int nsteps, int g_kind, const double* params,
+                    int nparams, void* stream);
+int setd_batch_tune(setd_batch* batch, void* stream);
+int setd_batch_set_tiles(setd_batch* batch, const int* cfg);
+int setd_batch_info(const setd_batch* batch, int64_t* info);
+
+/*
  * Norms for error reporting (deterministic fixed-order reductions):
  *   out[0] = ||x||_2, out[1] = ||x||_inf, and when y != NULL
  *   out[2] = ||x - y||_2, out[3] = ||x - y||_inf   (out is host, 4 doubles).

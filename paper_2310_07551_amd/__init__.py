@@ -17,7 +17,7 @@ from ._lib import (G_FHN, G_NONE, G_SCHNAKENBERG, PREC_BF16X2, PREC_BF16X3, PREC
                    STAGE_F, SetdError)
 
 __all__ = [
-    "phi_matrices", "tucker_apply", "Context", "field_norms", "profile_enable", "profile_read", "colmajor", "version", "SetdError",
+    "phi_matrices", "tucker_apply", "Context", "Batch", "field_norms", "profile_enable", "profile_read", "colmajor", "version", "SetdError",
     "G_NONE", "G_SCHNAKENBERG", "G_FHN", "PREC_F64", "PREC_F32", "PREC_BF16X3", "PREC_BF16X2", "STAGE_2", "STAGE_3",
     "STAGE_F",
 ]
@@ -203,3 +203,98 @@ class Context:
                                               _stream(stream)))
         self.tau = t
         return u
+
+
+class Batch:
+    """Many independent instances advanced together (setd_batch).
+
+    dims: sequence of per-instance grid sizes (each a tuple of d ints);
+    A: per instance, per component, per direction a column-major FP64 device
+    matrix (A[b][c][mu]).  The batch state is one flat FP64 device tensor in
+    the layout given by `layout()` (see setd.h)."""
+
+    def __init__(self, dims, A, tau: float, prec: int = PREC_F64, stream=None):
+        self.dims = [tuple(int(x) for x in dm) for dm in dims]
+        self.nbatch = len(self.dims)
+        if self.nbatch == 0:
+            raise ValueError("empty batch")
+        self.d = len(self.dims[0])
+        if any(len(dm) != self.d for dm in self.dims):
+            raise ValueError("every instance needs the same number of dimensions")
+        self.ncomp = len(A[0])
+        flat = []
+        for b in range(self.nbatch):
+            if len(A[b]) != self.ncomp:
+                raise ValueError("every instance needs the same number of components")
+            for c in range(self.ncomp):
+                for mu in range(self.d):
+                    _check_dev(A[b][c][mu], "A[%d][%d][%d]" % (b, c, mu))
+                    flat.append(A[b][c][mu].data_ptr())
+        ptrs = (ctypes.c_void_p * len(flat))(*flat)
+        cdims = (ctypes.c_int64 * (self.nbatch * self.d))(*[x for dm in self.dims for x in dm])
+        h = ctypes.c_void_p()
+        lib = _lib.load()
+        _lib.check(lib.setd_batch_create(ctypes.byref(h), self.nbatch, self.d, cdims, self.ncomp, ptrs, float(tau),
+                                         int(prec), _stream(stream)))
+        self._h = h
+        self.tau = float(tau)
+        off = (ctypes.c_int64 * (self.nbatch + 1))()
+        cs = (ctypes.c_int64 * self.nbatch)()
+        _lib.check(lib.setd_batch_layout(self._h, off, cs))
+        self.offsets = list(off)
+        self.cstride = list(cs)
+        self.total = self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().setd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def field(self, u, b: int, c: int):
+        """View of component c of instance b inside the flat state u (flat, N_b values)."""
+        n = 1
+        for x in self.dims[b]:
+            n *= x
+        o = self.offsets[b] + c * self.cstride[b]
+        return u[o:o + n]
+
+    def step(self, u, nsteps: int, g_kind: int, params, stream=None):
+        """Advance every instance by nsteps split-ETD3 steps, in place.  params:
+        one sequence of reaction parameters per instance (or one shared)."""
+        _check_dev(u, "u")
+        if u.numel() != self.total:
+            raise ValueError("u must hold %d values (layout())" % self.total)
+        params = list(params)
+        if params and not hasattr(params[0], "__len__"):
+            params = [params] * self.nbatch
+        if len(params) not in (0, self.nbatch):
+            raise ValueError("params: one entry per instance")
+        npar = len(params[0]) if params else 0
+        flat = [float(x) for p in params for x in p]
+        if any(len(p) != npar for p in params):
+            raise ValueError("every instance needs the same number of parameters")
+        arr = (ctypes.c_double * max(1, len(flat)))(*flat)
+        _lib.check(_lib.load().setd_batch_step(self._h, u.data_ptr(), int(nsteps), int(g_kind), arr, npar,
+                                               _stream(stream)))
+        return u
+
+    def tune(self, stream=None):
+        _lib.check(_lib.load().setd_batch_tune(self._h, _stream(stream)))
+        return self.info()
+
+    def set_tiles(self, mode1, modeB):
+        """mode1, modeB: (tm, tn, grid_cap) each."""
+        cfg = (ctypes.c_int * 6)(*[int(x) for x in tuple(mode1) + tuple(modeB)])
+        _lib.check(_lib.load().setd_batch_set_tiles(self._h, cfg))
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * _lib.BATCH_INFO)()
+        _lib.check(_lib.load().setd_batch_info(self._h, out))
+        return dict(mode1=tuple(out[0:3]), modeB=tuple(out[3:6]), tuned=bool(out[6]), launches_per_step=int(out[7]),
+                    total=int(out[8]), packed_sets=int(out[9]))

@@ -51,7 +51,17 @@ SIGNATURES = {
     "setd_version": (ctypes.c_char_p, []),
     "setd_profile_enable": (_c_int, [_c_int]),
     "setd_profile_read": (_c_int, [ctypes.POINTER(_c_double), _c_int]),
+    "setd_batch_create": (_c_int, [ctypes.POINTER(_vp), _c_int, _c_int, ctypes.POINTER(_c_i64), _c_int,
+                                   ctypes.POINTER(_vp), _c_double, _c_int, _vp]),
+    "setd_batch_destroy": (_c_int, [_vp]),
+    "setd_batch_layout": (_c_int, [_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i64)]),
+    "setd_batch_step": (_c_int, [_vp, _vp, _c_int, _c_int, ctypes.POINTER(_c_double), _c_int, _vp]),
+    "setd_batch_tune": (_c_int, [_vp, _vp]),
+    "setd_batch_set_tiles": (_c_int, [_vp, ctypes.POINTER(_c_int)]),
+    "setd_batch_info": (_c_int, [_vp, ctypes.POINTER(_c_i64)]),
 }
+
+BATCH_INFO = 10
 
 PROF_CLASSES = ("mode1_f64", "modeB_f64", "mode1_lp", "modeB_lp", "pointwise")
 

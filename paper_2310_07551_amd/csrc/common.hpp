@@ -102,6 +102,17 @@ __device__ __forceinline__ int find_job(const ModeJobs& J, int64_t t) {
   return lo;
 }
 
+// Same search over a job list in device memory (tile_begin ascending).
+__device__ __forceinline__ int find_job_list(const ModeJob* jobs, int njobs, int64_t t) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 enum class DType : int { F64 = 0, F32 = 1 };
 
 // ---- kernel timing (setd_profile_*), implemented in setd_api.hip ----
@@ -126,6 +137,28 @@ int launch_modeB_f64(ModeJobs& jobs, hipStream_t s);
 // (FP64 output adds the optional FP64 base).
 int launch_mode1_lp(ModeJobs& jobs, int prec, DType out, hipStream_t s);
 int launch_modeB_lp(ModeJobs& jobs, int prec, DType out, hipStream_t s);
+
+// Tile bookkeeping shared by the launchers and the batched work lists:
+// fills tiles_i / tiles_a / tile_begin for a TM x TN tile (16 TM rows of the
+// MFMA row index, 16 TN columns) and returns the total tile count.
+int64_t assign_tiles(ModeJob* jobs, int njobs, bool mode1, int TM, int TN);
+// Kernel variant a job can use: 0 = element loads with checks, 1 = vector
+// loads (aligned, extents a multiple of 4), 2 = interior fast path.
+int job_mode(const ModeJob& jb, bool mode1, int TM, int TN);
+
+// A work list in device memory (FP64): one persistent launch walks all tiles
+// of `njobs` jobs, each of which may belong to a different problem instance.
+// Every job of a list shares the regime, the tile shape and the variant.
+struct ModeList {
+  const ModeJob* jobs;   // device
+  int njobs;
+  int64_t total;         // tiles
+  bool mode1;
+  int tm, tn, mode;
+  int64_t grid_cap;      // maximum number of workgroups (0: one per tile)
+  double flops, bytes;   // algorithmic work, for the kernel timing
+};
+int launch_list_f64(const ModeList& L, hipStream_t s);
 
 // Algorithmic flops / bytes of a job table (2 N n per term; each input read
 // once, output written once, base read once; es = element sizes in bytes).

@@ -31,6 +31,7 @@
 // range of tiles (neighbouring tiles share X or L in that XCD's L2).
 #include "common.hpp"
 
+#include <algorithm>
 #include <cstdlib>
 
 namespace setd {
@@ -46,15 +47,12 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // ---------------------------------------------------------------------------
 // mode 1
 // ---------------------------------------------------------------------------
+// One wave computes tile `lt` of job `jb`.
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+__device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
   // MODE 0: element loads with bounds checks everywhere; 1: vector loads
   // (aligned operands); 2: additionally every tile interior and n % 32 == 0.
   constexpr bool VEC = MODE >= 1;
-  const int64_t t = remap_xcd(blockIdx.x, per_xcd);
-  if (t >= J.total_tiles) return;
-  const ModeJob& jb = J.job[find_job(J, t)];
-  const int64_t lt = t - jb.tile_begin;
   const int it = (int)(lt % jb.tiles_i);
   const int64_t bt = lt / jb.tiles_i;
 
@@ -181,16 +179,35 @@ __global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t
   }
 }
 
+// Job table in the kernel arguments (up to kMaxJobs outputs per launch).
+template <int TM, int TN, int MODE>
+__global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const int j = find_job(J, t);
+  mode1_tile<TM, TN, MODE>(J.job[j], t - J.job[j].tile_begin);
+}
+
+// Work list in device memory (any number of jobs, e.g. many independent
+// instances): a persistent grid walks the logical tiles with a stride that
+// keeps every block on its XCD's contiguous range.
+template <int TM, int TN, int MODE>
+__global__ void __launch_bounds__(64) mode1_f64_list_kernel(const ModeJob* __restrict__ jobs, int njobs,
+                                                            int64_t total, int64_t per_xcd) {
+  for (int64_t raw = blockIdx.x; raw < 8 * per_xcd; raw += gridDim.x) {
+    const int64_t t = remap_xcd(raw, per_xcd);
+    if (t >= total) continue;
+    const int j = find_job_list(jobs, njobs, t);
+    mode1_tile<TM, TN, MODE>(jobs[j], t - jobs[j].tile_begin);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // modes >= 2
 // ---------------------------------------------------------------------------
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+__device__ __forceinline__ void modeB_tile(const ModeJob& jb, int64_t lt) {
   constexpr bool VEC = MODE >= 1;   // as in the mode-1 kernel
-  const int64_t t = remap_xcd(blockIdx.x, per_xcd);
-  if (t >= J.total_tiles) return;
-  const ModeJob& jb = J.job[find_job(J, t)];
-  const int64_t lt = t - jb.tile_begin;
   const int it = (int)(lt % jb.tiles_i);
   const int64_t rest = lt / jb.tiles_i;
   const int64_t at = rest % jb.tiles_a;
@@ -352,9 +369,67 @@ __global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t
   }
 }
 
+template <int TM, int TN, int MODE>
+__global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+  const int64_t t = remap_xcd(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;
+  const int j = find_job(J, t);
+  modeB_tile<TM, TN, MODE>(J.job[j], t - J.job[j].tile_begin);
+}
+
+template <int TM, int TN, int MODE>
+__global__ void __launch_bounds__(64) modeB_f64_list_kernel(const ModeJob* __restrict__ jobs, int njobs,
+                                                            int64_t total, int64_t per_xcd) {
+  for (int64_t raw = blockIdx.x; raw < 8 * per_xcd; raw += gridDim.x) {
+    const int64_t t = remap_xcd(raw, per_xcd);
+    if (t >= total) continue;
+    const int j = find_job_list(jobs, njobs, t);
+    modeB_tile<TM, TN, MODE>(jobs[j], t - jobs[j].tile_begin);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+int64_t assign_tiles(ModeJob* jobs, int njobs, bool mode1, int TM, int TN) {
+  int64_t tot = 0;
+  for (int j = 0; j < njobs; ++j) {
+    ModeJob& jb = jobs[j];
+    if (mode1) {
+      jb.tiles_i = (int)ceil_div(jb.n, 16 * TM);
+      jb.tiles_a = (int)ceil_div(jb.nb, 16 * TN);     // tiles along b
+    } else {
+      jb.tiles_i = (int)ceil_div(jb.n, 16 * TN);
+      jb.tiles_a = (int)ceil_div(jb.na, 16 * TM);
+    }
+    jb.tile_begin = tot;
+    tot += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
+  }
+  return tot;
+}
+
+namespace {
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+bool no_interior() {
+  static const bool off = std::getenv("SETD_NO_INTERIOR_PATH") != nullptr;
+  return off;
+}
+}  // namespace
+
+int job_mode(const ModeJob& jb, bool mode1, int TM, int TN) {
+  bool vec, interior;
+  if (mode1) {
+    vec = (jb.n % 4 == 0) && aligned(jb.X[0], 32) && aligned(jb.Y, 16) && aligned(jb.base, 16);
+    interior = jb.n % 32 == 0 && jb.nb % (16 * TN) == 0;
+  } else {
+    vec = (jb.na % 4 == 0) && aligned(jb.Y, 16) && aligned(jb.base, 16);
+    for (int t = 0; t < jb.nterms; ++t) vec = vec && aligned(jb.X[t], 32);
+    interior = jb.n % 32 == 0 && jb.na % (16 * TM) == 0;
+  }
+  if (!vec) return 0;
+  return (interior && !no_interior()) ? 2 : 1;
+}
+
 namespace {
 
 struct TileCfg {
@@ -369,24 +444,9 @@ TileCfg env_tile(const char* name, TileCfg def) {
   return def;
 }
 
-bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
-
 int finish_tiles(ModeJobs& J, bool mode1, int TM, int TN) {
-  int64_t tot = 0;
-  for (int j = 0; j < J.njobs; ++j) {
-    ModeJob& jb = J.job[j];
-    if (mode1) {
-      jb.tiles_i = (int)ceil_div(jb.n, 16 * TM);
-      jb.tiles_a = (int)ceil_div(jb.nb, 16 * TN);     // tiles along b
-    } else {
-      jb.tiles_i = (int)ceil_div(jb.n, 16 * TN);
-      jb.tiles_a = (int)ceil_div(jb.na, 16 * TM);
-    }
-    jb.tile_begin = tot;
-    tot += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
-  }
-  J.total_tiles = tot;
-  J.tiles_per_job = J.njobs > 0 ? tot / J.njobs : 0;
+  J.total_tiles = assign_tiles(J.job, J.njobs, mode1, TM, TN);
+  J.tiles_per_job = J.njobs > 0 ? J.total_tiles / J.njobs : 0;
   for (int j = 0; j < J.njobs; ++j)
     if (J.job[j].tile_begin != (int64_t)j * J.tiles_per_job) J.tiles_per_job = 0;
   return SETD_OK;
@@ -418,20 +478,15 @@ void job_work(const ModeJobs& J, int es_in, int es_out, int es_mat, double& flop
 }
 
 int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
-  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{4, 2});
+  // default from a sweep on MI355X (FHN 128^3 and 256^3): 2 x 4 tiles
+  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{2, 4});
   finish_tiles(J, true, cfg.tm, cfg.tn);
   if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
   if (prof_on()) job_work(J, 8, 8, 8, fl, by);
   ProfScope prof(s, kProfMode1F64, fl, by);
-  bool vec = true;
-  for (int j = 0; j < J.njobs; ++j) {
-    const ModeJob& jb = J.job[j];
-    vec = vec && (jb.n % 4 == 0) && aligned(jb.X[0], 32) && aligned(jb.Y, 16) && aligned(jb.base, 16);
-  }
-  bool interior = vec && !std::getenv("SETD_NO_INTERIOR_PATH");
-  for (int j = 0; j < J.njobs; ++j) interior = interior && J.job[j].n % 32 == 0 && J.job[j].nb % (16 * cfg.tn) == 0;
-  const int mode = interior ? 2 : (vec ? 1 : 0);
+  int mode = 2;
+  for (int j = 0; j < J.njobs; ++j) mode = std::min(mode, job_mode(J.job[j], true, cfg.tm, cfg.tn));
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
   SETD_LAUNCH_MODES(mode1_f64_kernel, 4, 4)
@@ -443,21 +498,15 @@ int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
 }
 
 int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
-  const TileCfg cfg = env_tile("SETD_TILE_MODEB", TileCfg{2, 2});
+  // default from a sweep on MI355X (FHN 128^3 and 256^3): 4 x 2 tiles
+  const TileCfg cfg = env_tile("SETD_TILE_MODEB", TileCfg{4, 2});
   finish_tiles(J, false, cfg.tm, cfg.tn);
   if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
   if (prof_on()) job_work(J, 8, 8, 8, fl, by);
   ProfScope prof(s, kProfModeBF64, fl, by);
-  bool vec = true;
-  for (int j = 0; j < J.njobs; ++j) {
-    const ModeJob& jb = J.job[j];
-    vec = vec && (jb.na % 4 == 0) && aligned(jb.Y, 16) && aligned(jb.base, 16);
-    for (int t = 0; t < jb.nterms; ++t) vec = vec && aligned(jb.X[t], 32);
-  }
-  bool interior = vec && !std::getenv("SETD_NO_INTERIOR_PATH");
-  for (int j = 0; j < J.njobs; ++j) interior = interior && J.job[j].n % 32 == 0 && J.job[j].na % (16 * cfg.tm) == 0;
-  const int mode = interior ? 2 : (vec ? 1 : 0);
+  int mode = 2;
+  for (int j = 0; j < J.njobs; ++j) mode = std::min(mode, job_mode(J.job[j], false, cfg.tm, cfg.tn));
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
   SETD_LAUNCH_MODES(modeB_f64_kernel, 4, 4)
@@ -465,6 +514,42 @@ int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
   SETD_LAUNCH_MODES(modeB_f64_kernel, 2, 4)
   SETD_LAUNCH_MODES(modeB_f64_kernel, 2, 2)
   set_error("unsupported mode-b tile");
+  return SETD_EUNSUPPORTED;
+}
+
+#define SETD_LAUNCH_LIST(KERNEL, TM_, TN_)                                                     \
+  if (L.tm == TM_ && L.tn == TN_) {                                                           \
+    if (L.mode == 2)                                                                          \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 2>), grid, dim3(64), 0, s, L.jobs, L.njobs, L.total, per); \
+    else if (L.mode == 1)                                                                     \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 1>), grid, dim3(64), 0, s, L.jobs, L.njobs, L.total, per); \
+    else                                                                                      \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 0>), grid, dim3(64), 0, s, L.jobs, L.njobs, L.total, per); \
+    SETD_LAUNCHED();                                                                          \
+    return SETD_OK;                                                                           \
+  }
+
+int launch_list_f64(const ModeList& L, hipStream_t s) {
+  if (L.total == 0) return SETD_OK;
+  const int64_t per = ceil_div(L.total, 8);
+  // a multiple of 8 blocks, so that block b stays on XCD b % 8 through the
+  // whole loop; at most `grid_cap` blocks (0: one block per tile)
+  int64_t nblk = per * 8;
+  if (L.grid_cap > 0 && nblk > L.grid_cap) nblk = round_up(L.grid_cap, 8);
+  const dim3 grid((unsigned)nblk);
+  ProfScope prof(s, L.mode1 ? kProfMode1F64 : kProfModeBF64, L.flops, L.bytes);
+  if (L.mode1) {
+    SETD_LAUNCH_LIST(mode1_f64_list_kernel, 4, 4)
+    SETD_LAUNCH_LIST(mode1_f64_list_kernel, 4, 2)
+    SETD_LAUNCH_LIST(mode1_f64_list_kernel, 2, 4)
+    SETD_LAUNCH_LIST(mode1_f64_list_kernel, 2, 2)
+  } else {
+    SETD_LAUNCH_LIST(modeB_f64_list_kernel, 4, 4)
+    SETD_LAUNCH_LIST(modeB_f64_list_kernel, 4, 2)
+    SETD_LAUNCH_LIST(modeB_f64_list_kernel, 2, 4)
+    SETD_LAUNCH_LIST(modeB_f64_list_kernel, 2, 2)
+  }
+  set_error("unsupported tile %dx%d", L.tm, L.tn);
   return SETD_EUNSUPPORTED;
 }
 

@@ -13,8 +13,8 @@
 //                     The matrix is split once when it is packed; the tensor
 //                     operand is split in registers right after its load.
 //
-// Per-term scale factors multiply the FP32 tensor operand before any split,
-// so they never cost bf16 precision.
+// Per-term scale factors multiply FP32 partial sums (never a bf16 piece, and
+// never inside a load, where the multiply would make the wave wait for it).
 //
 // Operand layouts (probed on gfx950): FP32 16x16x4 and BF16 16x16x32 put
 // tile row 4 g + r in register r of lane (g, l); in the bf16 form lane (g, l)
@@ -61,19 +61,27 @@ __device__ __forceinline__ f4 mfma_bf(const bf8& a, const bf8& b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Cross products of order <= 2^-8 (NP = 2) or <= 2^-16 (NP = 3), smallest
-// first so the FP32 accumulator adds them before the leading term.
+// One k-chunk of the split product.  The bf16 matrix-core accumulation was
+// measured on gfx950 to round with a small bias toward zero (positive-data
+// mode products: mean relative error -2e-8 at n = 256, growing with the
+// number of chained accumulations; FP32 MFMA: 1e-10).  A bias does not average
+// out over the Tuckers and steps of the integrator, so the leading product
+// h*h is formed per chunk from a zero accumulator and added to `main` with an
+// FP32 VALU add (round to nearest), and the cross products of order <= 2^-8
+// (NP = 2) or <= 2^-16 (NP = 3) chain in their own, 2^8 times smaller,
+// accumulator `small` (unscaled; the caller applies the term's scale to it
+// once).  `main` receives sc * (chunk of h*h).
 template <int NP>
-__device__ __forceinline__ f4 mfma_split(const bf8 (&a)[NP], const bf8 (&b)[NP], f4 c) {
+__device__ __forceinline__ void mfma_split(const bf8 (&a)[NP], const bf8 (&b)[NP], float sc, f4& main,
+                                           f4& small) {
   if constexpr (NP == 3) {
-    c = mfma_bf(a[1], b[1], c);
-    c = mfma_bf(a[0], b[2], c);
-    c = mfma_bf(a[2], b[0], c);
+    small = mfma_bf(a[1], b[1], small);
+    small = mfma_bf(a[0], b[2], small);
+    small = mfma_bf(a[2], b[0], small);
   }
-  c = mfma_bf(a[0], b[1], c);
-  c = mfma_bf(a[1], b[0], c);
-  c = mfma_bf(a[0], b[0], c);
-  return c;
+  small = mfma_bf(a[0], b[1], small);
+  small = mfma_bf(a[1], b[0], small);
+  main += sc * mfma_bf(a[0], b[0], f4{0.f, 0.f, 0.f, 0.f});
 }
 
 // Writes `cnt` consecutive results starting at Y + off (all in range when
@@ -150,10 +158,10 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
       if (full) {
-        br[u] = vb[u] ? *(const f4*)(pb[u] + p0) * sc : f4{0.f, 0.f, 0.f, 0.f};
+        br[u] = vb[u] ? *(const f4*)(pb[u] + p0) : f4{0.f, 0.f, 0.f, 0.f};
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] * sc : 0.f;
+        for (int e = 0; e < 4; ++e) br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] : 0.f;
       }
     }
   };
@@ -163,13 +171,18 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
     f4 an[TM], bn[TN];
     const bool more = p0 + 16 < n;
     if (more) load(p0 + 16, an, bn);
+    // chunk sum from a zero accumulator, then scaled and added on the VALU
+    // (round to nearest): the rounding error of the long sum stays that of
+    // n/16 FP32 adds, which the eta cancellation of the splitting amplifies.
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
+    for (int m = 0; m < TM; ++m)
 #pragma unroll
-      for (int m = 0; m < TM; ++m)
+      for (int u = 0; u < TN; ++u) {
+        f4 t4 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int u = 0; u < TN; ++u)
-          acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][jj], bx[u][jj], acc[m][u], 0, 0, 0);
+        for (int jj = 0; jj < 4; ++jj) t4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][jj], bx[u][jj], t4, 0, 0, 0);
+        acc[m][u] += sc * t4;
+      }
     if (more) {
 #pragma unroll
       for (int m = 0; m < TM; ++m) a[m] = an[m];
@@ -224,41 +237,55 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
     const float* __restrict__ xb = (const float*)jb.X[term] + slab + arow + na * g;
     const float* __restrict__ pbp = (const float*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
     const float sc = (float)jb.scale[term];
-    auto load = [&](int p0, float* xr, float* pr) {
-      const bool vp = p0 + g < n;
-      const float* xs = xb + na * (int64_t)p0;
-      if (VEC && TM == 4 && lane_full && vp) {
-        const f4 v = *(const f4*)xs * sc;
+    // one k-chunk = 4 k-steps (16 values of p): operands of step k in
+    // xr[k], pr[k]
+    auto load = [&](int p0, float (*xr)[TM], float (*pr)[TN]) {
 #pragma unroll
-        for (int m = 0; m < TM; ++m) xr[m] = v[m];
-      } else if (VEC && TM == 2 && lane_full && vp) {
-        const f2 v = *(const f2*)xs * sc;
+      for (int k = 0; k < 4; ++k) {
+        const int p = p0 + 4 * k;
+        const bool vp = p + g < n;
+        const float* xs = xb + na * (int64_t)p;
+        if (VEC && TM == 4 && lane_full && vp) {
+          const f4 v = *(const f4*)xs;
 #pragma unroll
-        for (int m = 0; m < TM; ++m) xr[m] = v[m];
-      } else {
+          for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+        } else if (VEC && TM == 2 && lane_full && vp) {
+          const f2 v = *(const f2*)xs;
 #pragma unroll
-        for (int m = 0; m < TM; ++m) xr[m] = (vp && arow + m < na) ? xs[m] * sc : 0.f;
+          for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+        } else {
+#pragma unroll
+          for (int m = 0; m < TM; ++m) xr[k][m] = (vp && arow + m < na) ? xs[m] : 0.f;
+        }
+        const float* ps = pbp + (int64_t)ldp * p;   // padded: always in range
+#pragma unroll
+        for (int u = 0; u < TN; ++u) pr[k][u] = ps[u];
       }
-      const float* ps = pbp + (int64_t)ldp * p0;
-#pragma unroll
-      for (int u = 0; u < TN; ++u) pr[u] = ps[u];
     };
-    float xr[TM], pr[TN];
+    float xr[4][TM], pr[4][TN];
     load(0, xr, pr);
-    for (int p0 = 0; p0 < n; p0 += 4) {
-      float xn[TM], pn[TN];
-      const bool more = p0 + 4 < n;
-      if (more) load(p0 + 4, xn, pn);
+    for (int p0 = 0; p0 < n; p0 += 16) {
+      float xn[4][TM], pn[4][TN];
+      const bool more = p0 + 16 < n;
+      if (more) load(p0 + 16, xn, pn);
+      // chunk sum from a zero accumulator, scaled and added on the VALU
 #pragma unroll
       for (int m = 0; m < TM; ++m)
 #pragma unroll
-        for (int u = 0; u < TN; ++u)
-          acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[m], pr[u], acc[m][u], 0, 0, 0);
+        for (int u = 0; u < TN; ++u) {
+          f4 t4 = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) t4 = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[k][m], pr[k][u], t4, 0, 0, 0);
+          acc[m][u] += sc * t4;
+        }
       if (more) {
 #pragma unroll
-        for (int m = 0; m < TM; ++m) xr[m] = xn[m];
+        for (int k = 0; k < 4; ++k) {
 #pragma unroll
-        for (int u = 0; u < TN; ++u) pr[u] = pn[u];
+          for (int m = 0; m < TM; ++m) xr[k][m] = xn[k][m];
+#pragma unroll
+          for (int u = 0; u < TN; ++u) pr[k][u] = pn[k][u];
+        }
       }
     }
   }
@@ -312,11 +339,11 @@ __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_
     vb[u] = b < nb;
     pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + 8 * g;
   }
-  f4 acc[TM][TN];
+  f4 acc[TM][TN], accs[TM][TN];   // leading and cross products (see mfma_split)
 #pragma unroll
   for (int m = 0; m < TM; ++m)
 #pragma unroll
-    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < TN; ++u) acc[m][u] = accs[m][u] = f4{0.f, 0.f, 0.f, 0.f};
 
   for (int p0 = 0; p0 < n; p0 += 32) {
     bf8 ap[TM][NP], bp[TN][NP];
@@ -329,17 +356,17 @@ __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_
     for (int u = 0; u < TN; ++u) {
       f8 x;
       if (full && vb[u]) {
-        x = *(const f8*)(pb[u] + p0) * sc;
+        x = *(const f8*)(pb[u] + p0);
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = (vb[u] && p0 + 8 * g + e < n) ? pb[u][p0 + e] * sc : 0.f;
+        for (int e = 0; e < 8; ++e) x[e] = (vb[u] && p0 + 8 * g + e < n) ? pb[u][p0 + e] : 0.f;
       }
       split_bf16<NP>(x, bp[u]);
     }
 #pragma unroll
     for (int m = 0; m < TM; ++m)
 #pragma unroll
-      for (int u = 0; u < TN; ++u) acc[m][u] = mfma_split<NP>(ap[m], bp[u], acc[m][u]);
+      for (int u = 0; u < TN; ++u) mfma_split<NP>(ap[m], bp[u], sc, acc[m][u], accs[m][u]);
   }
   TOut* __restrict__ Y = (TOut*)jb.Y;
   const double* __restrict__ base = (const double*)jb.base;
@@ -351,7 +378,7 @@ __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r];
+      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r] + sc * accs[m][u][r];
     store_run<TOut>(Y, base, (b0 + 16 * u + l) * (int64_t)n + ir, v, 4 * TM, n - ir, VEC);
   }
 }
@@ -377,16 +404,27 @@ __global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_
   const int i0 = it * 16 * TN;
   const int64_t arow = a0 + TM * l;
   const bool lane_full = arow + TM <= na;
-  f4 acc[TM][TN];
+  f4 acc[TM][TN], accs[TM][TN];   // leading and cross products (see mfma_split)
 #pragma unroll
   for (int m = 0; m < TM; ++m)
 #pragma unroll
-    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < TN; ++u) acc[m][u] = accs[m][u] = f4{0.f, 0.f, 0.f, 0.f};
   const int64_t slab = na * (int64_t)n * b;
+  f4 acct[TM][TN];   // scaled cross products of the finished terms
+#pragma unroll
+  for (int m = 0; m < TM; ++m)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acct[m][u] = f4{0.f, 0.f, 0.f, 0.f};
   for (int term = 0; term < nterms; ++term) {
     const float* __restrict__ xb = (const float*)jb.X[term] + slab + arow;
     const __bf16* __restrict__ PH = (const __bf16*)jb.P[term];
     const float sc = (float)jb.scale[term];
+    if (term > 0) {
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+#pragma unroll
+        for (int u = 0; u < TN; ++u) accs[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+    }
     for (int p0 = 0; p0 < n; p0 += 32) {
       // tensor operand: 8 p values (8 g + j) x TM rows per lane
       f8 xm[TM];
@@ -398,14 +436,14 @@ __global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_
         if (VEC && TM == 4 && lane_full && vp) {
           const f4 v = *(const f4*)xs;
 #pragma unroll
-          for (int m = 0; m < TM; ++m) xm[m][j] = v[m] * sc;
+          for (int m = 0; m < TM; ++m) xm[m][j] = v[m];
         } else if (VEC && TM == 2 && lane_full && vp) {
           const f2 v = *(const f2*)xs;
 #pragma unroll
-          for (int m = 0; m < TM; ++m) xm[m][j] = v[m] * sc;
+          for (int m = 0; m < TM; ++m) xm[m][j] = v[m];
         } else {
 #pragma unroll
-          for (int m = 0; m < TM; ++m) xm[m][j] = (vp && arow + m < na) ? xs[m] * sc : 0.f;
+          for (int m = 0; m < TM; ++m) xm[m][j] = (vp && arow + m < na) ? xs[m] : 0.f;
         }
       }
       bf8 ap[TM][NP], bp[TN][NP];
@@ -420,8 +458,12 @@ __global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_
 #pragma unroll
       for (int m = 0; m < TM; ++m)
 #pragma unroll
-        for (int u = 0; u < TN; ++u) acc[m][u] = mfma_split<NP>(ap[m], bp[u], acc[m][u]);
+        for (int u = 0; u < TN; ++u) mfma_split<NP>(ap[m], bp[u], sc, acc[m][u], accs[m][u]);
     }
+#pragma unroll
+    for (int m = 0; m < TM; ++m)
+#pragma unroll
+      for (int u = 0; u < TN; ++u) acct[m][u] += sc * accs[m][u];
   }
   TOut* __restrict__ Y = (TOut*)jb.Y;
   const double* __restrict__ base = (const double*)jb.base;
@@ -434,26 +476,14 @@ __global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r];
+      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r] + acct[m][u][r];
     store_run<TOut>(Y, base, slab + na * (int64_t)i + ar, v, 4 * TM, (int)(na - ar < 4 * TM ? na - ar : 4 * TM),
                     VEC);
   }
 }
 
 int finish_tiles_lp(ModeJobs& J, bool mode1, int TM, int TN) {
-  int64_t tot = 0;
-  for (int j = 0; j < J.njobs; ++j) {
-    ModeJob& jb = J.job[j];
-    if (mode1) {
-      jb.tiles_i = (int)ceil_div(jb.n, 16 * TM);
-      jb.tiles_a = (int)ceil_div(jb.nb, 16 * TN);
-    } else {
-      jb.tiles_i = (int)ceil_div(jb.n, 16 * TN);
-      jb.tiles_a = (int)ceil_div(jb.na, 16 * TM);
-    }
-    jb.tile_begin = tot;
-    tot += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
-  }
+  const int64_t tot = assign_tiles(J.job, J.njobs, mode1, TM, TN);
   J.total_tiles = tot;
   J.tiles_per_job = J.njobs > 0 ? tot / J.njobs : 0;
   for (int j = 0; j < J.njobs; ++j)

@@ -152,14 +152,12 @@ __device__ __forceinline__ void reaction(const GParams& P, double u, double v, d
   }
 }
 
-// One thread per grid point.  u holds ncomp fields of N points.  Writes
-// G_c = g_c(u) and F_c = (K_c u_c) + G_c for every component, and (when
-// out_f_lp != nullptr) also F in FP32 for the reduced-precision Tuckers.
+// Per-point bodies.  u holds ncomp fields, component c at u + c * cs;
+// point idx has grid indices (i1, i2, i3) with i1 fastest.
 template <typename TF>
-__global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64_t N, int d, int n1, int n2,
-                                  int n3, StencilSet S, GParams gp, double* __restrict__ G, TF* __restrict__ F) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N) return;
+__device__ __forceinline__ void gf_point(const double* __restrict__ u, int64_t cs, int64_t idx, int ncomp, int d,
+                                         int n1, int n2, int n3, const StencilSet& S, const GParams& gp,
+                                         double* __restrict__ G, TF* __restrict__ F) {
   const int i1 = (int)(idx % n1);
   const int64_t r = idx / n1;
   const int i2 = (int)(r % n2);
@@ -170,10 +168,10 @@ __global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64
 
   double uc[2], g[2];
   uc[0] = u[idx];
-  uc[1] = (ncomp > 1) ? u[N + idx] : 0.0;
+  uc[1] = (ncomp > 1) ? u[cs + idx] : 0.0;
   reaction(gp, uc[0], uc[1], g[0], g[1]);
   for (int c = 0; c < ncomp; ++c) {
-    const double* __restrict__ uu = u + (int64_t)c * N;
+    const double* __restrict__ uu = u + (int64_t)c * cs;
     double k = 0.0;
     for (int mu = 0; mu < d; ++mu) {
       const int i = idxs[mu];
@@ -183,18 +181,42 @@ __global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64
       if (i + 1 < ns[mu]) t += S.up[off][i] * uu[idx + strides[mu]];
       k += t;
     }
-    G[(int64_t)c * N + idx] = g[c];
-    F[(int64_t)c * N + idx] = (TF)(k + g[c]);
+    G[(int64_t)c * cs + idx] = g[c];
+    F[(int64_t)c * cs + idx] = (TF)(k + g[c]);
   }
+}
+
+__device__ __forceinline__ void g_point(const double* __restrict__ u, int64_t cs, int64_t idx, int ncomp,
+                                        const GParams& gp, double* __restrict__ G) {
+  double g[2];
+  reaction(gp, u[idx], ncomp > 1 ? u[cs + idx] : 0.0, g[0], g[1]);
+  for (int c = 0; c < ncomp; ++c) G[(int64_t)c * cs + idx] = g[c];
+}
+
+template <typename TD>
+__device__ __forceinline__ void stage_d_point(const double* __restrict__ Us, const double* __restrict__ G,
+                                              int64_t cs, int64_t idx, int ncomp, const GParams& gp,
+                                              TD* __restrict__ D) {
+  double g[2];
+  reaction(gp, Us[idx], ncomp > 1 ? Us[cs + idx] : 0.0, g[0], g[1]);
+  for (int c = 0; c < ncomp; ++c) D[(int64_t)c * cs + idx] = (TD)(g[c] - G[(int64_t)c * cs + idx]);
+}
+
+// One thread per grid point.  Writes G_c = g_c(u) and F_c = (K_c u_c) + G_c
+// for every component (F in FP64, or FP32 for the reduced-precision Tuckers).
+template <typename TF>
+__global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64_t N, int d, int n1, int n2,
+                                  int n3, StencilSet S, GParams gp, double* __restrict__ G, TF* __restrict__ F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  gf_point<TF>(u, N, idx, ncomp, d, n1, n2, n3, S, gp, G, F);
 }
 
 // G_c = g_c(u) only (the dense-K path adds the mode products afterwards).
 __global__ void g_kernel(const double* __restrict__ u, int ncomp, int64_t N, GParams gp, double* __restrict__ G) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= N) return;
-  double g[2];
-  reaction(gp, u[idx], ncomp > 1 ? u[N + idx] : 0.0, g[0], g[1]);
-  for (int c = 0; c < ncomp; ++c) G[(int64_t)c * N + idx] = g[c];
+  g_point(u, N, idx, ncomp, gp, G);
 }
 
 // D_c = g_c(Us) - G_c.
@@ -203,9 +225,48 @@ __global__ void stage_d_kernel(const double* __restrict__ Us, const double* __re
                                GParams gp, TD* __restrict__ D) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= N) return;
-  double g[2];
-  reaction(gp, Us[idx], ncomp > 1 ? Us[N + idx] : 0.0, g[0], g[1]);
-  for (int c = 0; c < ncomp; ++c) D[(int64_t)c * N + idx] = (TD)(g[c] - G[(int64_t)c * N + idx]);
+  stage_d_point<TD>(Us, G, N, idx, ncomp, gp, D);
+}
+
+// ---- batched forms: one launch over the points of every instance ----
+// Blocks of 256 points never straddle two instances: instance b owns blocks
+// blk[b] .. blk[b+1]-1.
+__device__ __forceinline__ int find_inst(const int64_t* __restrict__ blk, int nbatch, int64_t block) {
+  int lo = 0, hi = nbatch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blk[mid] <= block) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// kind 0: G, F with the stencil; 1: G only; 2: D = g(U_s) - G
+__global__ void batch_pointwise_kernel(int kind, const BatchInstDev* __restrict__ inst, const int64_t* __restrict__ blk,
+                                       int nbatch, int ncomp, const double* __restrict__ x, double* __restrict__ G,
+                                       double* __restrict__ out) {
+  const int b = find_inst(blk, nbatch, blockIdx.x);
+  const BatchInstDev& I = inst[b];
+  const int64_t idx = (int64_t)(blockIdx.x - blk[b]) * blockDim.x + threadIdx.x;
+  if (idx >= I.N) return;
+  if (kind == 0)
+    gf_point<double>(x + I.off, I.cs, idx, ncomp, I.d, I.n[0], I.n[1], I.n[2], I.st, I.gp, G + I.off, out + I.off);
+  else if (kind == 1)
+    g_point(x + I.off, I.cs, idx, ncomp, I.gp, G + I.off);
+  else
+    stage_d_point<double>(x + I.off, G + I.off, I.cs, idx, ncomp, I.gp, out + I.off);
+}
+
+int launch_batch_pointwise(int kind, const BatchInstDev* inst, const int64_t* blk, int nbatch, int64_t nblocks,
+                           int ncomp, int64_t total_points, const double* x, double* G, double* out, hipStream_t s) {
+  if (nblocks == 0) return SETD_OK;
+  // kind 0 reads u, writes G and F; 1 reads u, writes G; 2 reads U_s and G, writes D
+  const double per = kind == 1 ? 16.0 : 24.0;
+  ProfScope prof(s, kProfPointwise, 0.0, per * (double)ncomp * (double)total_points);
+  hipLaunchKernelGGL(batch_pointwise_kernel, dim3((unsigned)nblocks), dim3(kBatchBlock), 0, s, kind, inst, blk,
+                     nbatch, ncomp, x, G, out);
+  SETD_LAUNCHED();
+  return SETD_OK;
 }
 
 int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* dims, const StencilSet& S,

@@ -21,6 +21,22 @@ struct StencilSet {
   const double* up[6];
 };
 
+// One instance of a batch as the batched pointwise kernels see it: its
+// fields start at element `off` of every batch-wide field buffer, component c
+// at off + c * cs.
+struct BatchInstDev {
+  int64_t off, cs, N;
+  int n[3];
+  int d;
+  GParams gp;
+  StencilSet st;   // tridiagonal coefficients (kind 0 only)
+};
+constexpr int kBatchBlock = 256;
+// kind 0: G = g(u), F = K u + G (stencil); 1: G = g(u); 2: out = g(x) - G.
+// blk[b] = first block of instance b (nbatch entries, ascending).
+int launch_batch_pointwise(int kind, const BatchInstDev* inst, const int64_t* blk, int nbatch, int64_t nblocks,
+                           int ncomp, int64_t total_points, const double* x, double* G, double* out, hipStream_t s);
+
 int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* dims, const StencilSet& S,
                       const GParams& gp, double* G, void* F, DType ftype, hipStream_t s);
 int launch_g(const double* u, int ncomp, int64_t N, const GParams& gp, double* G, hipStream_t s);

@@ -26,6 +26,7 @@
 #include "coeffs.hpp"
 #include "common.hpp"
 #include "pointwise.hpp"
+#include "api_util.hpp"
 
 namespace setd {
 
@@ -83,38 +84,7 @@ ProfScope::~ProfScope() {
 
 namespace {
 
-// Bank entries of Algorithms 1-2: (stage, ell) pairs.
-const int kBankStage[5] = {SETD_STAGE_2, SETD_STAGE_3, SETD_STAGE_3, SETD_STAGE_F, SETD_STAGE_F};
-const int kBankEll[5] = {1, 1, 2, 1, 2};
 
-int bank_index(int stage, int ell) {
-  for (int e = 0; e < 5; ++e)
-    if (kBankStage[e] == stage && kBankEll[e] == ell) return e;
-  return -1;
-}
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  int alloc(size_t b) {
-    release();
-    if (b == 0) return SETD_OK;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      p = nullptr;
-      set_error("hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
-      return SETD_ENOMEM;
-    }
-    bytes = b;
-    return SETD_OK;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  ~DevBuf() { release(); }
-};
 
 }  // namespace
 }  // namespace setd
@@ -156,21 +126,6 @@ struct setd_ctx {
 
 namespace {
 
-ModeJob mk_job(const void* X, const void* P, double scale, void* Y, const void* base, int64_t na, int n,
-               int64_t nb) {
-  ModeJob j{};
-  j.X[0] = X;
-  j.P[0] = P;
-  j.scale[0] = scale;
-  j.nterms = 1;
-  j.Y = Y;
-  j.base = base;
-  j.na = na;
-  j.nb = nb;
-  j.n = n;
-  j.ldp = packed_ld(n);
-  return j;
-}
 
 // One Tucker-summed output: Y = base + sum_t scale_t T(X_t, {P_t[mu]}).
 struct TuckerTerm {
@@ -275,12 +230,6 @@ int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int pre
   return flush(J, klast, s);
 }
 
-bool is_tridiagonal(const std::vector<double>& A, int n) {
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i)
-      if ((i - j > 1 || j - i > 1) && A[i + (size_t)n * j] != 0.0) return false;
-  return true;
-}
 
 int build_bank(setd_ctx* c, hipStream_t s) {
   const int d = c->d;
@@ -384,38 +333,7 @@ int build_bank(setd_ctx* c, hipStream_t s) {
   return SETD_OK;
 }
 
-int make_gparams(int g_kind, const double* params, int nparams, int ncomp, GParams& gp) {
-  gp.kind = g_kind;
-  gp.p[0] = gp.p[1] = gp.p[2] = 0.0;
-  gp.p[3] = 1.0;
-  if (g_kind == SETD_G_NONE) {
-    SETD_CHECK_ARG(nparams == 0 || params != nullptr, "params is NULL");
-    return SETD_OK;
-  }
-  SETD_CHECK_ARG(ncomp == 2, "reaction kind %d needs two components", g_kind);
-  SETD_CHECK_ARG(params != nullptr, "params is NULL");
-  if (g_kind == SETD_G_SCHNAKENBERG) {
-    SETD_CHECK_ARG(nparams == 3, "Schnakenberg takes 3 parameters (gamma, a, b)");
-  } else if (g_kind == SETD_G_FHN) {
-    SETD_CHECK_ARG(nparams == 3 || nparams == 4, "FitzHugh-Nagumo takes 3 or 4 parameters (eps, a1, a0[, rho])");
-  } else {
-    SETD_CHECK_ARG(false, "unknown reaction kind %d", g_kind);
-  }
-  for (int k = 0; k < nparams; ++k) {
-    if (!std::isfinite(params[k])) {
-      set_error("reaction parameter %d is not finite", k);
-      return SETD_ENONFINITE;
-    }
-    gp.p[k] = params[k];
-  }
-  return SETD_OK;
-}
 
-bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-  const char* x = (const char*)a;
-  const char* y = (const char*)b;
-  return x < y + nb && y < x + na;
-}
 
 // Split phi action outputs for the F group: stage s, ell = 1.
 // G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type.

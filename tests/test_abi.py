@@ -67,6 +67,20 @@ def test_validation_errors_before_any_launch():
     assert lib.setd_tucker_apply(None, None, 2, dd, M, 1.0, 0.0, 0, None, 0, None) == _lib.SETD_EINVAL
     out = (ctypes.c_double * 4)()
     assert lib.setd_field_norms(None, None, 10, out, None) == _lib.SETD_EINVAL
+    # batch: bad sizes, NULL matrices, reduced precision (FP64 only)
+    bd = (ctypes.c_int64 * 4)(16, 16, 1, 16)
+    BA = (ctypes.c_void_p * 8)(*([1] * 8))
+    assert lib.setd_batch_create(ctypes.byref(h), 0, 2, bd, 2, BA, 0.01, 0, None) == _lib.SETD_EINVAL
+    assert lib.setd_batch_create(ctypes.byref(h), 2, 2, bd, 2, BA, 0.01, 0, None) == _lib.SETD_EINVAL   # n = 1
+    bd[2] = 16
+    assert lib.setd_batch_create(ctypes.byref(h), 2, 2, bd, 2, (ctypes.c_void_p * 8)(), 0.01, 0,
+                                 None) == _lib.SETD_EINVAL
+    assert lib.setd_batch_create(ctypes.byref(h), 2, 2, bd, 2, BA, 0.01, _lib.PREC_F32,
+                                 None) == _lib.SETD_EUNSUPPORTED
+    assert lib.setd_batch_step(None, None, 1, 0, p, 0, None) == _lib.SETD_EINVAL
+    info = (ctypes.c_int64 * _lib.BATCH_INFO)()
+    assert lib.setd_batch_info(None, info) == _lib.SETD_EINVAL
+    assert lib.setd_batch_set_tiles(None, (ctypes.c_int * 6)(2, 2, 0, 2, 2, 0)) == _lib.SETD_EINVAL
 
 
 def test_python_binding_raises_on_error():

@@ -140,6 +140,24 @@ def random_matrix(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
 
 # Workloads used by tests and the bench (sizes, parameters and step counts of
 # the three benchmark configurations).
+BATCH_SIDES = (64, 96, 128, 192, 256, 384, 512)
+
+
+def schnakenberg_batch(nbatch: int = 64, *, sides: Sequence[int] = BATCH_SIDES, dv_range=(8.0, 12.0),
+                       seed: int = 12345, tau: float = 1e-3, nsteps: int = 100) -> List[Problem]:
+    """Batch of independent 2D Schnakenberg instances of uneven size: each side
+    drawn from `sides` (non-square grids allowed), d_v ~ U(dv_range), both
+    from a PCG64 stream seeded with `seed`; instance k draws its initial noise
+    from seeds 2k (u) and 2k+1 (v).  Kinetics and tau as the 64 x 64 case."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(nbatch):
+        n1, n2 = (int(x) for x in rng.choice(np.asarray(sides), size=2))
+        dv = float(rng.uniform(*dv_range))
+        out.append(schnakenberg_2d(n1, n2, dv=dv, tau=tau, nsteps=nsteps, instance=k))
+    return out
+
+
 CONFIGS: Dict[str, dict] = {
     "schnakenberg2d_64": dict(builder="schnakenberg_2d", kwargs=dict(n1=64)),
     "fhn3d_128": dict(builder="fhn_3d", kwargs=dict(n=128, nsteps=100)),
