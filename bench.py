@@ -111,6 +111,75 @@ def cpu_baseline(prob, nsteps):
                 (nsteps, prob.name, "x".join(map(str, prob.dims)), dt))
 
 
+def run_batch(torch, setd, wl, warmup=3, serial_steps=10):
+    """Batching form: 64 independent 2D Schnakenberg instances of uneven size
+    (sides from {64, ..., 512}, d_v ~ U(8, 12)), FP64, tau = 1e-3, 100 steps.
+    Timed with graph replay (no kernel events), then once more with kernel
+    events for the per-class rates, then the same instances stepped one
+    context at a time for comparison."""
+    probs = wl.schnakenberg_batch()
+    nsteps = probs[0].nsteps
+    dev = torch.device("cuda:0")
+    A = [[[torch.from_numpy(M.ravel(order="F").copy()).to(dev) for M in Ac] for Ac in p.A] for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = setd.Batch([p.dims for p in probs], A, probs[0].tau)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    info = B.tune()
+    tune_s = time.perf_counter() - t0
+    u0 = torch.zeros(B.total, dtype=torch.float64, device=dev)
+    for b, p in enumerate(probs):
+        for c in range(2):
+            B.field(u0, b, c).copy_(torch.from_numpy(p.U0[c].ravel(order="F").copy()))
+    params = [p.params for p in probs]
+    u = u0.clone()
+    B.step(u, warmup, probs[0].g_kind, params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(u, nsteps, probs[0].g_kind, params)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = bool(torch.isfinite(u).all())
+    # per-class rates (direct launches with events)
+    setd.profile_enable(True)
+    setd.profile_read(reset=True)
+    B.step(u, 5, probs[0].g_kind, params)
+    torch.cuda.synchronize()
+    prof = setd.profile_read(reset=True)
+    setd.profile_enable(False)
+    info = B.info()
+    B.close()
+    flops = sum(mode_flops_per_step(p.dims, 2) for p in probs)
+    mode_ms = (prof["mode1_f64"]["ms"] + prof["modeB_f64"]["ms"]) / 5
+    # the same instances one context at a time (graph replay per context)
+    ctxs = [setd.Context(p.dims, A[b], p.tau) for b, p in enumerate(probs)]
+    us = [torch.cat([B.field(u0, b, 0), B.field(u0, b, 1)]).clone() for b in range(len(probs))]
+    for b, p in enumerate(probs):
+        ctxs[b].step(us[b], 1, p.g_kind, p.params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, p in enumerate(probs):
+        ctxs[b].step(us[b], serial_steps, p.g_kind, p.params)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    res = dict(workload="schnakenberg2d_batch64", instances=len(probs), steps=nsteps, finite=ok,
+               steps_per_s=round(nsteps / dt, 3), ms_per_step=round(dt / nsteps * 1e3, 4),
+               instance_steps_per_s=round(len(probs) * nsteps / dt, 1),
+               tucker_flops_per_step=flops, tucker_tflops=round(flops / (dt / nsteps) / 1e12, 3),
+               mode_kernel_tflops=round(flops / (mode_ms * 1e-3) / 1e12, 3) if mode_ms > 0 else None,
+               launches_per_step=info["launches_per_step"], tiles=dict(mode1=info["mode1"], modeB=info["modeB"]),
+               packed_sets=info["packed_sets"], setup_s=round(setup, 3), tune_s=round(tune_s, 3),
+               one_context_at_a_time_steps_per_s=round(serial_steps / dts, 3),
+               speedup_vs_one_context_at_a_time=round((nsteps / dt) / (serial_steps / dts), 2))
+    log("batch: %.1f steps/s (%d instances), %.2f x one context at a time" %
+        (res["steps_per_s"], len(probs), res["speedup_vs_one_context_at_a_time"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,8 +190,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of this size (HBM counter calibration) and exit")
-    ap.add_argument("--forms", default="f64,f32,bf16x3,bf16x2",
-                    help="arithmetic forms to time (f64 always runs; f32, bf16x3, bf16x2 are compared against it)")
+    ap.add_argument("--forms", default="f64,f32,bf16x3,bf16x2,batch",
+                    help="forms to time besides the FP64 metric: f32, bf16x3, bf16x2 (compared against f64) and "
+                         "batch (64 uneven 2D Schnakenberg instances, 100 steps)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -176,7 +246,7 @@ def main():
         sys.exit(1)
 
     forms = {}
-    for name in [f for f in args.forms.split(",") if f and f != "f64"]:
+    for name in [f for f in args.forms.split(",") if f and f not in ("f64", "batch")]:
         prec = {"f32": setd.PREC_F32, "bf16x3": setd.PREC_BF16X3, "bf16x2": setd.PREC_BF16X2}[name]
         phi_l, dt_l, prof_l, u_l = run_form(prec, args.steps, args.warmup)
         errs = [setd.field_norms(u_l[c * prob.N:(c + 1) * prob.N], u[c * prob.N:(c + 1) * prob.N]) for c in range(2)]
@@ -188,6 +258,8 @@ def main():
                            tucker_tflops=round(fl / (ms * 1e-3) / 1e12, 3) if ms > 0 else None,
                            phi_setup_s=round(phi_l, 3))
         log("%s: %.2f steps/s, rel_l2 vs f64 %s" % (name, args.steps / dt_l, forms[name]["rel_l2_vs_f64"]))
+
+    batch = run_batch(torch, setd, wl) if "batch" in args.forms.split(",") else None
 
     steps_per_s = args.steps / dt
     nterms = 2 if prob.d == 2 else 3
@@ -236,6 +308,7 @@ def main():
         "tucker_flops_per_step": flops_step,
         "kernels": kernels,
         "precision_forms": forms,
+        "batch_form": batch,
         "roofline": roof,
         "cpu_baseline": None,
     }

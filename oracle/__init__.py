@@ -12,6 +12,9 @@ Contents
   tensor  - mu-mode product, Tucker operator, Kronecker-sum action (Section 2)
   etd     - reaction terms, phi bank, split phi action, eq. (exprk3) step
   norms   - relative L2 / inf errors
+  adjoint - discrete adjoint of the step (vector-Jacobian product), loss
+            gradients with respect to U0, reaction parameters and diffusion
+            scale (import as oracle.adjoint)
 
 Every function is pinned by tests/test_oracle_*.py against facts fixed by the
 paper or by mathematics (closed forms, brute-force Kronecker products, exact
