@@ -184,6 +184,35 @@ int setd_etd2_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
                    const double* params, int nparams, void* stream);
 
 /*
+ * Adjoint of one split-ETD3 step (vector-Jacobian product), for gradients of
+ * a loss of the final state.  With U' = step(U; params, sigma) the step of
+ * setd_etd_step (eq. exprk3 with the split phi actions) and
+ * ubar = dL/dU' on entry, on return
+ *     ubar = dL/dU = (dU'/dU)^T ubar_in,
+ *     grad[k]            += (dU'/dparams_k)^T ubar_in     (k < nparams),
+ *     grad[nparams + c]  += (dU'/dsigma_c)^T ubar_in      (bit c of sigma_mask),
+ * where sigma_c scales every A_mu^(c) (derivative at sigma_c = 1; for
+ * A^(c) = d_c D this is d_c dL/dd_c).  The transposed split actions are
+ * Tucker operators with the transposed phi matrices (Section 2, eq.
+ * krontomu); the phi derivative uses z phi_l'(z) = phi_{l-1}(z) - l phi_l(z).
+ *
+ *   u           state U at the start of the step (ncomp*N, device, read only).
+ *   ubar        ncomp*N (device), in place; must not overlap u.
+ *   g_kind, params, nparams   as for setd_etd_step (the same values).
+ *   sigma_mask  components whose diffusion-size gradient is wanted (0..3);
+ *               each costs 2d extra Tucker groups.
+ *   grad        device accumulators (nparams + ncomp doubles), added to,
+ *               never cleared; reduced in a fixed order (deterministic).
+ * FP64 contexts only (SETD_EUNSUPPORTED otherwise).  The first call builds
+ * the transposed and derivative phi matrices (synchronising); device memory
+ * grows by about 11 ncomp N doubles.  Checkpointing is the caller's: keep
+ * U at the start of each step (or recompute it) and call this backwards.
+ */
+int setd_etd_adjoint_step(setd_ctx* ctx, const double* u, double* ubar, int g_kind,
+                          const double* params, int nparams, int sigma_mask, double* grad,
+                          void* stream);
+
+/*
  * Batched integration: nbatch independent instances of one kind of problem
  * (same d, ncomp and tau; each with its own grid, matrices A_mu^(c) and
  * reaction parameters) advanced together by split-ETD3 steps (the same step

@@ -191,6 +191,23 @@ class Context:
         self.tau = t
         return u
 
+    def adjoint_step(self, u, ubar, g_kind: int, params: Sequence[float], grad, sigma_mask: int = 0,
+                     stream=None):
+        """One step backwards: ubar <- (dU'/dU)^T ubar at state u; grad (FP64
+        device, len(params) + ncomp) accumulates the parameter and diffusion-size
+        gradients (setd_etd_adjoint_step)."""
+        _check_dev(u, "u")
+        _check_dev(ubar, "ubar")
+        _check_dev(grad, "grad")
+        if u.numel() != self.ncomp * self.N or ubar.numel() != u.numel():
+            raise ValueError("u and ubar must hold ncomp*N values")
+        if grad.numel() < len(params) + self.ncomp:
+            raise ValueError("grad needs len(params) + ncomp entries")
+        p = (ctypes.c_double * max(1, len(params)))(*[float(x) for x in params])
+        _lib.check(_lib.load().setd_etd_adjoint_step(self._h, u.data_ptr(), ubar.data_ptr(), int(g_kind), p,
+                                                     len(params), int(sigma_mask), grad.data_ptr(), _stream(stream)))
+        return ubar
+
     def step2(self, u, nsteps: int, g_kind: int, params: Sequence[float], tau: Optional[float] = None,
               stream=None):
         """Advance u by nsteps steps of the second-order split integrator etd2rkds, in place."""

@@ -51,6 +51,8 @@ SIGNATURES = {
     "setd_version": (ctypes.c_char_p, []),
     "setd_profile_enable": (_c_int, [_c_int]),
     "setd_profile_read": (_c_int, [ctypes.POINTER(_c_double), _c_int]),
+    "setd_etd_adjoint_step": (_c_int, [_vp, _vp, _vp, _c_int, ctypes.POINTER(_c_double), _c_int, _c_int, _vp,
+                                       _vp]),
     "setd_batch_create": (_c_int, [ctypes.POINTER(_vp), _c_int, _c_int, ctypes.POINTER(_c_i64), _c_int,
                                    ctypes.POINTER(_vp), _c_double, _c_int, _vp]),
     "setd_batch_destroy": (_c_int, [_vp]),

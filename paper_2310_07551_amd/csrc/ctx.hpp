@@ -1,0 +1,81 @@
+// The integration context (setd_ctx of setd.h) and the Tucker-group runner
+// shared by the forward step (setd_api.hip) and the adjoint step
+// (adjoint.hip).  Internal to libsetd.
+#pragma once
+
+#include <vector>
+
+#include "api_util.hpp"
+#include "coeffs.hpp"
+#include "common.hpp"
+#include "pointwise.hpp"
+
+struct setd_ctx {
+  int d = 0, ncomp = 0, prec = SETD_PREC_F64;
+  int dims[3] = {1, 1, 1};
+  int64_t N = 0;
+  double tau = 0.0;
+  std::vector<double> Ah[2][3];
+  bool tridiag = false;
+  setd::StencilSet st{};
+  setd::Splitting sp[3];
+  int nterms = 0;
+  void* bank[2][5][3][3] = {};   // [comp][entry][term][mu] packed FP64 matrix
+  void* Apk[2][3] = {};          // packed A for the dense K path
+  void* bank2[2][2][3] = {};     // [comp][ell-1][mu] phi_ell(tau A_mu) for etd2rkds
+  double *G = nullptr, *F = nullptr, *U2 = nullptr, *U3 = nullptr, *W = nullptr, *D = nullptr;
+  double* Y1[2][9] = {};
+  double* Y2[2][9] = {};
+  double* aux = nullptr;         // FP32 copy of a split_phi_apply input (reduced precision)
+  setd::DevBuf A_mem, stencil_mem, bank_mem, work_mem;
+  // one captured step (hipGraph), replayed per step on an internal stream
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  double* g_u = nullptr;
+  setd::GParams g_gp{};
+  const void* g_fn = nullptr;    // which step function the graph holds
+  // adjoint step (set up by its first call; rebuilt when tau changes)
+  double adj_tau = 0.0;
+  setd::DevBuf adj_bank_mem, adj_mem;
+  void* bankT[2][5][3][3] = {};   // transposed phi matrices, packed for the forward kernels
+  void* dbank[2][5][3][3] = {};   // d/dsigma phi matrices at sigma = 1
+  void* ApkT[2][3] = {};          // transposed A (dense K path)
+  double *aD2 = nullptr, *aD3 = nullptr, *Fbar = nullptr, *Dbar = nullptr, *Gbar = nullptr;
+  double *U3bar = nullptr, *U2bar = nullptr, *Ef = nullptr, *E3 = nullptr, *E2 = nullptr, *KtF = nullptr;
+  double* part = nullptr;         // per-block partial sums of the gradient reductions
+  ~setd_ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
+};
+
+namespace setd {
+
+// One Tucker-summed output: Y = base + sum_t scale_t T(X_t, {P_t[mu]}).
+struct TuckerTerm {
+  const void* X;        // FP64, or FP32 for the reduced-precision forms
+  void* const* P;       // d packed matrices (layout per pack_for)
+  double scale;
+  void* Y1;             // intermediates, same type as X
+  void* Y2;
+};
+struct TuckerOut {
+  double* Y;
+  const double* base;
+  int nterms;
+  TuckerTerm term[kMaxTerms];
+};
+
+// Runs all outputs of a group: d grouped launches (or more if a launch would
+// exceed kMaxJobs).  dims has d >= 2 entries.  With a reduced-precision
+// `prec`, term inputs and Y1/Y2 are FP32 and the outputs FP64.
+int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s);
+// Packs a matrix for the mode kernels of the given arithmetic and direction.
+int pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s);
+// G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type.
+int compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s);
+
+}  // namespace setd

@@ -27,6 +27,7 @@
 #include "common.hpp"
 #include "pointwise.hpp"
 #include "api_util.hpp"
+#include "ctx.hpp"
 
 namespace setd {
 
@@ -91,56 +92,10 @@ namespace {
 
 using namespace setd;
 
-struct setd_ctx {
-  int d = 0, ncomp = 0, prec = SETD_PREC_F64;
-  int dims[3] = {1, 1, 1};
-  int64_t N = 0;
-  double tau = 0.0;
-  std::vector<double> Ah[2][3];
-  bool tridiag = false;
-  StencilSet st{};
-  Splitting sp[3];
-  int nterms = 0;
-  void* bank[2][5][3][3] = {};   // [comp][entry][term][mu] packed FP64 matrix
-  void* Apk[2][3] = {};          // packed A for the dense K path
-  void* bank2[2][2][3] = {};     // [comp][ell-1][mu] phi_ell(tau A_mu) for etd2rkds
-  double *G = nullptr, *F = nullptr, *U2 = nullptr, *U3 = nullptr, *W = nullptr, *D = nullptr;
-  double* Y1[2][9] = {};
-  double* Y2[2][9] = {};
-  double* aux = nullptr;         // FP32 copy of a split_phi_apply input (reduced precision)
-  DevBuf A_mem, stencil_mem, bank_mem, work_mem;
-  // one captured step (hipGraph), replayed per step on an internal stream
-  hipStream_t gstream = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  double* g_u = nullptr;
-  GParams g_gp{};
-  const void* g_fn = nullptr;    // which step function the graph holds
-  ~setd_ctx() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (ev_in) (void)hipEventDestroy(ev_in);
-    if (ev_out) (void)hipEventDestroy(ev_out);
-    if (gstream) (void)hipStreamDestroy(gstream);
-  }
-};
 
 namespace {
 
 
-// One Tucker-summed output: Y = base + sum_t scale_t T(X_t, {P_t[mu]}).
-struct TuckerTerm {
-  const void* X;        // FP64, or FP32 for the reduced-precision forms
-  void* const* P;       // d packed matrices (layout per pack_for)
-  double scale;
-  void* Y1;             // intermediates, same type as X
-  void* Y2;
-};
-struct TuckerOut {
-  double* Y;
-  const double* base;
-  int nterms;
-  TuckerTerm term[kMaxTerms];
-};
 
 // How a table of jobs is launched: which regime, which arithmetic, and the
 // output type (FP64 for the last mode of a Tucker; the reduced-precision
@@ -171,16 +126,22 @@ int push(ModeJobs& J, const ModeJob& jb, const LaunchKind& k, hipStream_t s) {
 
 // Packs a matrix for the mode kernels of the given arithmetic: mode 1 reads
 // it row-major; modes >= 2 column-major (FP64, FP32) or row-major (bf16).
-int pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s) {
+}  // namespace
+
+int setd::pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s) {
   if (prec == SETD_PREC_F64) return pack_matrix_f64(M, n, scale, mu == 0, (double*)out, s);
   if (prec == SETD_PREC_F32) return pack_matrix_f32(M, n, scale, mu == 0, (float*)out, s);
   return pack_matrix_bf16(M, n, scale, true, prec == SETD_PREC_BF16X3 ? 3 : 2, out, s);
 }
 
+namespace {
+
 // Runs all outputs of a group: d grouped launches (or more if a launch
 // would exceed kMaxJobs).  dims has d >= 2 entries.  With a reduced-precision
 // `prec`, term inputs and Y1/Y2 are FP32 and the outputs FP64.
-int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s) {
+}  // namespace
+
+int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s) {
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) N *= dims[mu];
   const DType mid = prec == SETD_PREC_F64 ? DType::F64 : DType::F32;
@@ -229,6 +190,8 @@ int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int pre
   }
   return flush(J, klast, s);
 }
+
+namespace {
 
 
 int build_bank(setd_ctx* c, hipStream_t s) {
@@ -337,7 +300,9 @@ int build_bank(setd_ctx* c, hipStream_t s) {
 
 // Split phi action outputs for the F group: stage s, ell = 1.
 // G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type.
-int compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+}  // namespace
+
+int setd::compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
   const int d = c->d, nc = c->ncomp;
   const int64_t N = c->N;
   const bool lp = c->prec != SETD_PREC_F64;
@@ -368,6 +333,8 @@ int compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
   }
   return SETD_OK;
 }
+
+namespace {
 
 // One exprk3ds_real step (the time loop of Algorithms 1 and 2).
 int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {

@@ -1,0 +1,138 @@
+"""GPU adjoint step (setd_etd_adjoint_step) and the checkpointed
+differentiable integration (paper_2310_07551_amd.autograd) against the
+oracle's discrete adjoint on small grids (FP64, 1e-11 relative), and against
+central finite differences of the GPU forward run on the 3D FitzHugh-Nagumo
+128^3, 200-step workload (h = 1e-6)."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from tests.gpu_util import dev, rel_l2, say, torch
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+import paper_2310_07551_amd as setd   # noqa: E402
+from paper_2310_07551_amd import autograd as sad   # noqa: E402
+
+TOL = 1e-11
+
+
+def _flat(U):
+    return np.concatenate([np.asarray(x).ravel(order="F") for x in U])
+
+
+def _small(kind):
+    if kind == "fhn3d":
+        p = wl.fhn_3d(dims=(12, 10, 9))
+        p.U0 = [0.3 * np.random.default_rng(5 + c).standard_normal(x.shape) for c, x in enumerate(p.U0)]
+        return p, 6
+    if kind == "schnak2d":
+        p = wl.schnakenberg_2d(20, 17, tau=2e-3)
+        p.U0 = [x + 0.05 * np.random.default_rng(3 + c).standard_normal(x.shape) for c, x in enumerate(p.U0)]
+        return p, 5
+    # dense (non-tridiagonal), non-symmetric matrices: exercises the transposes
+    p = wl.schnakenberg_2d(14, 18, tau=2e-3)
+    rng = np.random.default_rng(8)
+    p.A = [[M + 5.0 * np.triu(rng.standard_normal(M.shape), 1) / M.shape[0] for M in Ac] for Ac in p.A]
+    p.U0 = [x + 0.05 * rng.standard_normal(x.shape) for x in p.U0]
+    return p, 4
+
+
+@pytest.mark.parametrize("kind", ["fhn3d", "schnak2d", "dense"])
+def test_adjoint_matches_oracle(kind):
+    p, n = _small(kind)
+    rng = np.random.default_rng(11)
+    target = [x + 0.1 * rng.standard_normal(x.shape) for x in p.U0]
+    L, U0bar, pbar, sig = oadj.loss_and_gradients(p.U0, p.A, p.tau, n, p.g_kind, p.params, target)
+    say("adjoint", kind, p.dims, n, "L", L)
+    # GPU: forward states, then adjoint steps backwards through them (C-ABI level)
+    T = torch()
+    ctx = setd.Context(p.dims, [[dev(M) for M in Ac] for Ac in p.A], p.tau)
+    u = T.from_numpy(_flat(p.U0)).cuda()
+    states = [u.clone()]
+    for _ in range(n):
+        ctx.step(u, 1, p.g_kind, p.params)
+        states.append(u.clone())
+    ubar = states[-1] - T.from_numpy(_flat(target)).cuda()
+    grad = T.zeros(len(p.params) + 2, dtype=T.float64, device="cuda")
+    for k in range(n - 1, -1, -1):
+        ctx.adjoint_step(states[k], ubar, p.g_kind, p.params, grad, sigma_mask=3)
+    T.cuda.synchronize()
+    e_u = rel_l2(ubar.cpu().numpy(), _flat(U0bar))
+    g = grad.cpu().numpy()
+    e_p = np.abs(g[:len(p.params)] - pbar) / np.maximum(np.abs(pbar), 1e-300)
+    e_s = np.abs(g[len(p.params):] - sig) / np.abs(sig)
+    say("  ubar rel_l2 %.2e  params %s  sigma %s" % (e_u, e_p, e_s))
+    assert e_u < TOL
+    assert np.all(np.abs(g[:len(p.params)] - pbar) <= TOL * np.max(np.abs(pbar)))
+    assert np.all(e_s < TOL)
+
+
+def test_autograd_checkpointed_matches_oracle():
+    p, n = _small("fhn3d")
+    n = 7
+    rng = np.random.default_rng(12)
+    target = [x + 0.1 * rng.standard_normal(x.shape) for x in p.U0]
+    L, U0bar, pbar, sig = oadj.loss_and_gradients(p.U0, p.A, p.tau, n, p.g_kind, p.params, target)
+    T = torch()
+    D = [[dev(wl.neumann_d2(m)) for m in p.dims] for _ in range(2)]
+    diff = T.tensor([p.A[0][0][1, 1] / wl.neumann_d2(p.dims[0])[1, 1],
+                     p.A[1][0][1, 1] / wl.neumann_d2(p.dims[0])[1, 1]], dtype=T.float64, requires_grad=True)
+    params = T.tensor(p.params, dtype=T.float64, requires_grad=True)
+    u0 = T.from_numpy(_flat(p.U0)).cuda().requires_grad_(True)
+    uT = sad.integrate(u0, params, diff, dims=p.dims, D=D, g_kind=p.g_kind, tau=p.tau, nsteps=n, checkpoint=3)
+    loss = 0.5 * ((uT - T.from_numpy(_flat(target)).cuda()) ** 2).sum()
+    loss.backward()
+    assert abs(loss.item() - L) <= 1e-12 * L
+    assert rel_l2(u0.grad.cpu().numpy(), _flat(U0bar)) < TOL
+    gp = params.grad.numpy()
+    assert np.all(np.abs(gp - pbar) <= TOL * np.max(np.abs(pbar)))
+    # oracle sigma gradient = diff * dL/ddiff
+    gd = diff.grad.numpy() * diff.detach().numpy()
+    assert np.all(np.abs(gd - sig) <= TOL * np.abs(sig))
+
+
+def test_fhn128_200_steps_gradients_vs_central_differences():
+    """3D FitzHugh-Nagumo 128^3, 200 steps, L = 1/2 ||u(T) - u_target||^2 with
+    u_target from eps = 0.55, a1 = 2.1; adjoint gradients (checkpoint every 20
+    steps) against central differences h = 1e-6 of the GPU forward run."""
+    T = torch()
+    p = wl.make("fhn3d_128", nsteps=200)
+    nsteps = 200
+    D = [[dev(wl.neumann_d2(m)) for m in p.dims] for _ in range(2)]
+    du, dv = 1.0, float(p.A[1][0][1, 1] / wl.neumann_d2(p.dims[0])[1, 1])
+    eps, a1, a0 = p.params[:3]
+    u0 = T.from_numpy(p.u0_flat()).cuda()
+
+    def run(u_init, e, a, dvv):
+        with T.no_grad():
+            return sad.integrate(u_init, T.tensor([e, a, a0], dtype=T.float64), T.tensor([du, dvv], dtype=T.float64),
+                                 dims=p.dims, D=D, g_kind=p.g_kind, tau=p.tau, nsteps=nsteps, checkpoint=nsteps)
+
+    target = run(u0, 0.55, 2.1, dv).clone()
+
+    def loss_of(u_init, e, a, dvv):
+        return 0.5 * float(((run(u_init, e, a, dvv) - target) ** 2).sum().item())
+
+    params = T.tensor([eps, a1, a0], dtype=T.float64, requires_grad=True)
+    diff = T.tensor([du, dv], dtype=T.float64, requires_grad=True)
+    ui = u0.clone().requires_grad_(True)
+    uT = sad.integrate(ui, params, diff, dims=p.dims, D=D, g_kind=p.g_kind, tau=p.tau, nsteps=nsteps, checkpoint=20)
+    loss = 0.5 * ((uT - target) ** 2).sum()
+    loss.backward()
+    say("loss", loss.item(), "dL/deps", params.grad[0].item(), "dL/da1", params.grad[1].item(),
+        "dL/ddv", diff.grad[1].item())
+    h = 1e-6
+    fd_eps = (loss_of(u0, eps + h, a1, dv) - loss_of(u0, eps - h, a1, dv)) / (2 * h)
+    fd_a1 = (loss_of(u0, eps, a1 + h, dv) - loss_of(u0, eps, a1 - h, dv)) / (2 * h)
+    fd_dv = (loss_of(u0, eps, a1, dv + h) - loss_of(u0, eps, a1, dv - h)) / (2 * h)
+    dirn = T.from_numpy(np.random.default_rng(3).standard_normal(u0.numel())).cuda()
+    fd_u = (loss_of(u0 + h * dirn, eps, a1, dv) - loss_of(u0 - h * dirn, eps, a1, dv)) / (2 * h)
+    ad_u = float((ui.grad * dirn).sum().item())
+    pairs = [("eps", fd_eps, params.grad[0].item()), ("a1", fd_a1, params.grad[1].item()),
+             ("dv", fd_dv, diff.grad[1].item()), ("u0 direction", fd_u, ad_u)]
+    for name, fd, ad in pairs:
+        say("  %-13s fd %.10e adjoint %.10e rel %.2e" % (name, fd, ad, abs(fd - ad) / abs(fd)))
+    for name, fd, ad in pairs:
+        assert abs(fd - ad) <= 1e-5 * abs(fd), name
