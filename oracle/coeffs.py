@@ -9,6 +9,10 @@ Test infrastructure only (see the package docstring).
   alpha_{1,mu}; alpha is the same for every direction mu and eta_2 carries
   the factor 2^{d-3}.
 
+* Table 1 complex column and Table 2 (two-term, complex coefficients, any
+  d >= 2, used by exprk3ds_cplx): the upper signs; the lower signs are the
+  complex conjugates and give the same real part of every split action.
+
 Each function returns (ells, eta, alpha) with
     ells  : tuple of the phi indices l_i of the terms,
     eta   : array (nterms,) of eta_{i,d},
@@ -64,6 +68,54 @@ def table3_real(ell: int, d: int):
     eta = np.array([e1, e2, e3])
     alpha = np.array([[a1] * d, [a2] * d, [a3] * d])
     return (1, 2, 1), eta, alpha
+
+
+def table1_complex(ell: int):
+    """Table 1, complex column (upper signs), for phi_ell with ell in {1, 2}."""
+    if ell == 1:
+        s2 = math.sqrt(2.0)
+        eta = [7.0 / 4.0 + 1.5 * s2 * 1j, -3.0 - 6.0 * s2 * 1j]
+        a1 = 12.0 / 11.0 - 4.0 * s2 / 11.0 * 1j
+        a2 = 4.0 / 3.0 - 2.0 * s2 / 3.0 * 1j
+    elif ell == 2:
+        s3 = math.sqrt(3.0)
+        eta = [2.0 / 3.0 + 2.0 * s3 / 3.0 * 1j, -2.0 / 3.0 - 8.0 * s3 / 3.0 * 1j]
+        a1 = 3.0 / 4.0 - s3 / 4.0 * 1j
+        a2 = 6.0 / 7.0 - 3.0 * s3 / 7.0 * 1j
+    else:
+        raise ValueError("Table 1 covers ell = 1, 2")
+    return (1, 2), np.array(eta), np.array([[a1, a1], [a2, a2]])
+
+
+def table2_complex(ell: int, d: int):
+    """Table 2 (upper signs) for phi_ell (ell in {1, 2}) in dimension d >= 2:
+    alpha is the same in every direction, eta_2 carries 2^{d-2}."""
+    if d < 2:
+        raise ValueError("directional splitting needs d >= 2")
+    scale = 2.0 ** (d - 2)
+    if ell == 1:
+        r = math.sqrt(2.0)
+        e1 = 7.0 / 4.0 + 3.0 * r / 2.0 * 1j
+        e2 = scale * (-3.0 - 6.0 * r * 1j)
+        a1 = 12.0 / 11.0 - 4.0 * r / 11.0 * 1j
+        a2 = 4.0 / 3.0 - 2.0 * r / 3.0 * 1j
+    elif ell == 2:
+        r = math.sqrt(3.0)
+        e1 = 2.0 / 3.0 + 2.0 * r / 3.0 * 1j
+        e2 = scale * (-2.0 / 3.0 - 8.0 * r / 3.0 * 1j)
+        a1 = 3.0 / 4.0 - r / 4.0 * 1j
+        a2 = 6.0 / 7.0 - 3.0 * r / 7.0 * 1j
+    else:
+        raise ValueError("Table 2 covers ell = 1, 2")
+    return (1, 2), np.array([e1, e2]), np.array([[a1] * d, [a2] * d])
+
+
+def split_coefficients_cplx(ell: int, d: int):
+    """The complex splitting used by exprk3ds_cplx: Table 1's complex column
+    for d = 2, Table 2 for d > 2."""
+    if d == 2:
+        return table1_complex(ell)
+    return table2_complex(ell, d)
 
 
 def split_coefficients(ell: int, d: int):

@@ -19,7 +19,7 @@ from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
 
-from .coeffs import split_coefficients
+from .coeffs import split_coefficients, split_coefficients_cplx
 from .phi import phi
 from .tensor import kron_sum_action, tucker
 
@@ -56,21 +56,29 @@ def reaction(kind: int, U: Sequence[np.ndarray], params: Sequence[float]) -> Lis
 
 class PhiBank:
     """P_{i,s}^(l){mu} = phi_{l_i}(c_s tau alpha_{i,mu}^(l) A_mu) for one
-    component, with the matching eta_i^(l)."""
+    component, with the matching eta_i^(l).
 
-    def __init__(self, As: Sequence[np.ndarray], tau: float):
+    variant "real": exprk3ds_real (Table 1 real columns for d = 2, Table 3
+    for d > 2).  variant "cplx": exprk3ds_cplx (Table 1 complex column for
+    d = 2, Table 2 for d > 2): the phi matrices and the sum over the terms are
+    complex and a split action returns the real part of that sum (the exact
+    phi_l(tau K) v is real; the imaginary part is O(tau^3))."""
+
+    def __init__(self, As: Sequence[np.ndarray], tau: float, variant: str = "real"):
         self.d = len(As)
         self.tau = tau
+        self.variant = variant
+        coef = split_coefficients if variant == "real" else split_coefficients_cplx
         self.mats: Dict[Tuple, List[np.ndarray]] = {}
         self.eta: Dict[int, np.ndarray] = {}
         self.ells: Dict[int, Tuple[int, ...]] = {}
         cache: Dict[Tuple, np.ndarray] = {}
         for ell in (1, 2):
-            ells, eta, _ = split_coefficients(ell, self.d)
+            ells, eta, _ = coef(ell, self.d)
             self.eta[ell] = eta
             self.ells[ell] = ells
         for (s, ell) in BANK_ENTRIES:
-            ells, _, alpha = split_coefficients(ell, self.d)
+            ells, _, alpha = coef(ell, self.d)
             for i, li in enumerate(ells):
                 mats = []
                 for mu, A in enumerate(As):
@@ -83,10 +91,10 @@ class PhiBank:
 
     def split_apply(self, ell: int, s, V: np.ndarray) -> np.ndarray:
         """S_l(c_s tau) V = sum_i eta_i^(l) T(V, {P_{i,s}^(l){mu}})."""
-        out = np.zeros_like(V)
+        out = np.zeros(V.shape, dtype=np.complex128 if self.variant == "cplx" else np.float64)
         for i in range(len(self.ells[ell])):
             out = out + self.eta[ell][i] * tucker(V, self.mats[(s, ell, i)])
-        return out
+        return out.real.copy() if self.variant == "cplx" else out
 
 
 def etd_step(U: Sequence[np.ndarray], As: Sequence[Sequence[np.ndarray]], banks: Sequence[PhiBank],
@@ -106,14 +114,15 @@ def etd_step(U: Sequence[np.ndarray], As: Sequence[Sequence[np.ndarray]], banks:
             + 1.5 * tau * banks[c].split_apply(2, "f", D3[c]) for c in range(nc)]
 
 
-def make_banks(As: Sequence[Sequence[np.ndarray]], tau: float) -> List[PhiBank]:
-    return [PhiBank(Ac, tau) for Ac in As]
+def make_banks(As: Sequence[Sequence[np.ndarray]], tau: float, variant: str = "real") -> List[PhiBank]:
+    return [PhiBank(Ac, tau, variant) for Ac in As]
 
 
 def integrate(U0: Sequence[np.ndarray], As: Sequence[Sequence[np.ndarray]], tau: float, nsteps: int,
-              kind: int, params: Sequence[float], banks=None) -> List[np.ndarray]:
-    """nsteps steps of size tau from U0 (constant step size, as in the algorithms)."""
-    banks = make_banks(As, tau) if banks is None else banks
+              kind: int, params: Sequence[float], banks=None, variant: str = "real") -> List[np.ndarray]:
+    """nsteps steps of size tau from U0 (constant step size, as in the
+    algorithms); variant "real" (exprk3ds_real) or "cplx" (exprk3ds_cplx)."""
+    banks = make_banks(As, tau, variant) if banks is None else banks
     U = [np.array(x, dtype=np.float64, order="F") for x in U0]
     for _ in range(nsteps):
         U = etd_step(U, As, banks, tau, kind, params)

@@ -26,12 +26,14 @@ import scipy.linalg
 
 
 def phi_all(X: np.ndarray, p: int) -> List[np.ndarray]:
-    """[phi_0(X), ..., phi_p(X)] for a square FP64 matrix X."""
-    X = np.asarray(X, dtype=np.float64)
+    """[phi_0(X), ..., phi_p(X)] for a square FP64 matrix X (real, or complex
+    for the complex-coefficient splittings of Table 2)."""
+    X = np.asarray(X)
+    X = X.astype(np.complex128 if np.iscomplexobj(X) else np.float64)
     n = X.shape[0]
     if X.shape != (n, n):
         raise ValueError("X must be square")
-    W = np.zeros(((p + 1) * n, (p + 1) * n))
+    W = np.zeros(((p + 1) * n, (p + 1) * n), dtype=X.dtype)
     W[:n, :n] = X
     for j in range(p):
         W[j * n:(j + 1) * n, (j + 1) * n:(j + 2) * n] = np.eye(n)
