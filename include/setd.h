@@ -184,6 +184,20 @@ int setd_etd2_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
                    const double* params, int nparams, void* stream);
 
 /*
+ * exprk3ds_cplx: the same step with the two-term complex splitting (Table 1
+ * complex column for d = 2, Table 2 for d > 2; Algorithm 1's complex
+ * variant), each split action taken as the real part of its two complex
+ * Tucker operators (the exact phi action is real; the imaginary part is
+ * O(tau^3)).  Same context, arguments and in-place semantics as
+ * setd_etd_step.  FP64 contexts only.  The first call (and a call with a new
+ * tau) builds the complex phi matrices, through the real 2n x 2n
+ * representation of the complex matrices, and synchronises; device memory
+ * grows by 12 (d = 2) or 24 (d = 3) N doubles per component.
+ */
+int setd_etd_cplx_step(setd_ctx* ctx, double* u, int nsteps, double tau, int g_kind,
+                       const double* params, int nparams, void* stream);
+
+/*
  * Adjoint of one split-ETD3 step (vector-Jacobian product), for gradients of
  * a loss of the final state.  With U' = step(U; params, sigma) the step of
  * setd_etd_step (eq. exprk3 with the split phi actions) and

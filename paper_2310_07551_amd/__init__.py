@@ -191,6 +191,19 @@ class Context:
         self.tau = t
         return u
 
+    def step_cplx(self, u, nsteps: int, g_kind: int, params: Sequence[float], tau: Optional[float] = None,
+                  stream=None):
+        """Advance u by nsteps exprk3ds_cplx steps (complex two-term splitting), in place."""
+        _check_dev(u, "u")
+        if u.numel() != self.ncomp * self.N:
+            raise ValueError("u must hold ncomp*N values")
+        p = (ctypes.c_double * max(1, len(params)))(*[float(x) for x in params])
+        t = self.tau if tau is None else float(tau)
+        _lib.check(_lib.load().setd_etd_cplx_step(self._h, u.data_ptr(), int(nsteps), t, int(g_kind), p, len(params),
+                                                  _stream(stream)))
+        self.tau = t
+        return u
+
     def adjoint_step(self, u, ubar, g_kind: int, params: Sequence[float], grad, sigma_mask: int = 0,
                      stream=None):
         """One step backwards: ubar <- (dU'/dU)^T ubar at state u; grad (FP64

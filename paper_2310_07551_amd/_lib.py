@@ -45,6 +45,7 @@ SIGNATURES = {
     "setd_split_phi_apply": (_c_int, [_vp, _c_int, _c_int, _c_int, _vp, _vp, _c_double, _c_double, _vp]),
     "setd_etd_step": (_c_int, [_vp, _vp, _c_int, _c_double, _c_int, ctypes.POINTER(_c_double), _c_int, _vp]),
     "setd_etd2_step": (_c_int, [_vp, _vp, _c_int, _c_double, _c_int, ctypes.POINTER(_c_double), _c_int, _vp]),
+    "setd_etd_cplx_step": (_c_int, [_vp, _vp, _c_int, _c_double, _c_int, ctypes.POINTER(_c_double), _c_int, _vp]),
     "setd_field_norms": (_c_int, [_vp, _vp, _c_i64, ctypes.POINTER(_c_double), _vp]),
     "setd_last_error": (ctypes.c_char_p, []),
     "setd_sync": (_c_int, [_vp]),

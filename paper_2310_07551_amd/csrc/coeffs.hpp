@@ -76,6 +76,42 @@ inline Splitting splitting(int ell, int d) {
   return S;
 }
 
+// Two-term splitting with complex coefficients (exprk3ds_cplx): the complex
+// column of Table 1 for d = 2 and Table 2 for d > 2 (which reduces to it at
+// d = 2), upper signs; ell_i = (1, 2); alpha is the same in every direction.
+// The conjugate set gives the same real part of every split action.
+struct SplittingC {
+  double eta_r[2], eta_i[2];
+  double al_r[2], al_i[2];
+};
+
+inline SplittingC splitting_cplx(int ell, int d) {
+  SplittingC S{};
+  const double pw = std::ldexp(1.0, d - 2);
+  if (ell == 1) {
+    const double q = std::sqrt(2.0);
+    S.eta_r[0] = 7.0 / 4.0;
+    S.eta_i[0] = 1.5 * q;
+    S.eta_r[1] = -3.0 * pw;
+    S.eta_i[1] = -6.0 * q * pw;
+    S.al_r[0] = 12.0 / 11.0;
+    S.al_i[0] = -4.0 * q / 11.0;
+    S.al_r[1] = 4.0 / 3.0;
+    S.al_i[1] = -2.0 * q / 3.0;
+  } else {
+    const double q = std::sqrt(3.0);
+    S.eta_r[0] = 2.0 / 3.0;
+    S.eta_i[0] = 2.0 * q / 3.0;
+    S.eta_r[1] = -2.0 / 3.0 * pw;
+    S.eta_i[1] = -8.0 * q / 3.0 * pw;
+    S.al_r[0] = 0.75;
+    S.al_i[0] = -q / 4.0;
+    S.al_r[1] = 6.0 / 7.0;
+    S.al_i[1] = -3.0 * q / 7.0;
+  }
+  return S;
+}
+
 // Argument scale c_s of the stages of eq. exprk3.
 inline double stage_scale(int stage) {
   return stage == 2 ? 1.0 / 3.0 : (stage == 3 ? 2.0 / 3.0 : 1.0);

@@ -44,6 +44,11 @@ struct setd_ctx {
   double *aD2 = nullptr, *aD3 = nullptr, *Fbar = nullptr, *Dbar = nullptr, *Gbar = nullptr;
   double *U3bar = nullptr, *U2bar = nullptr, *Ef = nullptr, *E3 = nullptr, *E2 = nullptr, *KtF = nullptr;
   double* part = nullptr;         // per-block partial sums of the gradient reductions
+  // exprk3ds_cplx (set up by its first step; rebuilt when tau changes)
+  double cplx_tau = 0.0;
+  setd::DevBuf cplx_bank_mem, cplx_mem;
+  void* cbank[2][5][2][3][2] = {};   // [comp][entry][term][mu][re, im]; last mu: eta folded in
+  double* cY[2][24] = {};            // complex intermediates (re, im planes)
   ~setd_ctx() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -77,5 +82,11 @@ int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int pre
 int pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s);
 // G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type.
 int compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s);
+// Launches FP64 mode-product jobs of one regime in groups of kMaxJobs.
+int launch_f64_jobs(std::vector<ModeJob>& jobs, bool mode1, hipStream_t s);
+// exprk3ds_cplx (cplx.hip): complex phi bank for step size tau (synchronises
+// s; no-op when already built for tau) and one step.
+int prepare_cplx(setd_ctx* c, double tau, hipStream_t s);
+int step_cplx_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s);
 
 }  // namespace setd

@@ -141,6 +141,21 @@ namespace {
 // `prec`, term inputs and Y1/Y2 are FP32 and the outputs FP64.
 }  // namespace
 
+int setd::launch_f64_jobs(std::vector<ModeJob>& jobs, bool mode1, hipStream_t s) {
+  ModeJobs J;
+  J.njobs = 0;
+  for (const ModeJob& jb : jobs) {
+    J.job[J.njobs++] = jb;
+    if (J.njobs == kMaxJobs) {
+      SETD_TRY(mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s));
+      J.njobs = 0;
+    }
+  }
+  if (J.njobs) SETD_TRY(mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s));
+  jobs.clear();
+  return SETD_OK;
+}
+
 int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s) {
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) N *= dims[mu];
@@ -879,6 +894,19 @@ int setd_etd2_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, c
                    void* stream) {
   clear_error();
   return run_steps(c, u, nsteps, tau, g_kind, params, nparams, (hipStream_t)stream, step2_once);
+}
+
+int setd_etd_cplx_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params,
+                       int nparams, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(c != nullptr, "ctx is NULL");
+  SETD_CHECK_ARG(tau > 0.0 && std::isfinite(tau), "tau must be positive and finite");
+  if (c->prec != SETD_PREC_F64) {
+    set_error("exprk3ds_cplx runs in FP64 only");
+    return SETD_EUNSUPPORTED;
+  }
+  if (nsteps > 0) SETD_TRY(prepare_cplx(c, tau, (hipStream_t)stream));
+  return run_steps(c, u, nsteps, tau, g_kind, params, nparams, (hipStream_t)stream, step_cplx_once);
 }
 
 int setd_field_norms(const double* x, const double* y, int64_t n, double* out, void* stream) {
