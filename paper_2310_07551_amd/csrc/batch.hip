@@ -424,19 +424,34 @@ struct PlanBuilder {
     group(d_group(bank_index(SETD_STAGE_F, 2), 1.5 * tau, u, B->W));
   }
 
-  // Uploads every list into `mem` and points the list ops at it.
+  // Uploads every list (job records, then the array of first tiles) into
+  // `mem` and points the list ops at it.
   int upload(DevBuf& mem, std::vector<Op>& out) {
     size_t njobs = 0;
     for (const auto& l : lists) njobs += l.size();
     std::vector<ModeJob> all;
+    std::vector<int64_t> begins;
     all.reserve(njobs);
-    for (const auto& l : lists) all.insert(all.end(), l.begin(), l.end());
-    if (mem.bytes < njobs * sizeof(ModeJob)) SETD_TRY(mem.alloc(std::max<size_t>(njobs, 1) * sizeof(ModeJob)));
-    if (njobs) SETD_HIP(hipMemcpy(mem.p, all.data(), njobs * sizeof(ModeJob), hipMemcpyHostToDevice));
+    begins.reserve(njobs);
+    for (const auto& l : lists)
+      for (const ModeJob& jb : l) {
+        all.push_back(jb);
+        begins.push_back(jb.tile_begin);
+      }
+    const size_t jbytes = round_up((int64_t)(njobs * sizeof(ModeJob)), 256);
+    const size_t need = std::max<size_t>(jbytes + njobs * sizeof(int64_t), 256);
+    if (mem.bytes < need) SETD_TRY(mem.alloc(need));
+    const ModeJob* jdev = (const ModeJob*)mem.p;
+    const int64_t* bdev = (const int64_t*)((char*)mem.p + jbytes);
+    if (njobs) {
+      SETD_HIP(hipMemcpy(mem.p, all.data(), njobs * sizeof(ModeJob), hipMemcpyHostToDevice));
+      SETD_HIP(hipMemcpy((void*)bdev, begins.data(), njobs * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
     size_t at = 0, li = 0;
     for (Op& op : ops)
       if (op.list) {
-        op.L.jobs = (const ModeJob*)mem.p + at;
+        op.L.jobs = jdev + at;
+        op.L.begins = bdev + at;
         at += lists[li++].size();
       }
     out = ops;

@@ -102,12 +102,14 @@ __device__ __forceinline__ int find_job(const ModeJobs& J, int64_t t) {
   return lo;
 }
 
-// Same search over a job list in device memory (tile_begin ascending).
-__device__ __forceinline__ int find_job_list(const ModeJob* jobs, int njobs, int64_t t) {
+// Same search for a job list in device memory, over its compact array of
+// first tiles (ascending): 8 bytes per job, so the array of a whole batch
+// stays in the scalar cache while the job records themselves do not.
+__device__ __forceinline__ int find_job_list(const int64_t* begins, int njobs, int64_t t) {
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].tile_begin <= t) lo = mid;
+    if (begins[mid] <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -151,6 +153,7 @@ int job_mode(const ModeJob& jb, bool mode1, int TM, int TN);
 // Every job of a list shares the regime, the tile shape and the variant.
 struct ModeList {
   const ModeJob* jobs;   // device
+  const int64_t* begins; // device: jobs[j].tile_begin
   int njobs;
   int64_t total;         // tiles
   bool mode1;

@@ -192,12 +192,13 @@ __global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t
 // instances): a persistent grid walks the logical tiles with a stride that
 // keeps every block on its XCD's contiguous range.
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) mode1_f64_list_kernel(const ModeJob* __restrict__ jobs, int njobs,
+__global__ void __launch_bounds__(64) mode1_f64_list_kernel(const ModeJob* __restrict__ jobs,
+                                                            const int64_t* __restrict__ begins, int njobs,
                                                             int64_t total, int64_t per_xcd) {
   for (int64_t raw = blockIdx.x; raw < 8 * per_xcd; raw += gridDim.x) {
     const int64_t t = remap_xcd(raw, per_xcd);
     if (t >= total) continue;
-    const int j = find_job_list(jobs, njobs, t);
+    const int j = find_job_list(begins, njobs, t);
     mode1_tile<TM, TN, MODE>(jobs[j], t - jobs[j].tile_begin);
   }
 }
@@ -378,12 +379,13 @@ __global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t
 }
 
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) modeB_f64_list_kernel(const ModeJob* __restrict__ jobs, int njobs,
+__global__ void __launch_bounds__(64) modeB_f64_list_kernel(const ModeJob* __restrict__ jobs,
+                                                            const int64_t* __restrict__ begins, int njobs,
                                                             int64_t total, int64_t per_xcd) {
   for (int64_t raw = blockIdx.x; raw < 8 * per_xcd; raw += gridDim.x) {
     const int64_t t = remap_xcd(raw, per_xcd);
     if (t >= total) continue;
-    const int j = find_job_list(jobs, njobs, t);
+    const int j = find_job_list(begins, njobs, t);
     modeB_tile<TM, TN, MODE>(jobs[j], t - jobs[j].tile_begin);
   }
 }
@@ -520,11 +522,11 @@ int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
 #define SETD_LAUNCH_LIST(KERNEL, TM_, TN_)                                                     \
   if (L.tm == TM_ && L.tn == TN_) {                                                           \
     if (L.mode == 2)                                                                          \
-      hipLaunchKernelGGL((KERNEL<TM_, TN_, 2>), grid, dim3(64), 0, s, L.jobs, L.njobs, L.total, per); \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 2>), grid, dim3(64), 0, s, L.jobs, L.begins, L.njobs, L.total, per); \
     else if (L.mode == 1)                                                                     \
-      hipLaunchKernelGGL((KERNEL<TM_, TN_, 1>), grid, dim3(64), 0, s, L.jobs, L.njobs, L.total, per); \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 1>), grid, dim3(64), 0, s, L.jobs, L.begins, L.njobs, L.total, per); \
     else                                                                                      \
-      hipLaunchKernelGGL((KERNEL<TM_, TN_, 0>), grid, dim3(64), 0, s, L.jobs, L.njobs, L.total, per); \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 0>), grid, dim3(64), 0, s, L.jobs, L.begins, L.njobs, L.total, per); \
     SETD_LAUNCHED();                                                                          \
     return SETD_OK;                                                                           \
   }
