@@ -86,12 +86,13 @@ __device__ __forceinline__ void mfma_split(const bf8 (&a)[NP], const bf8 (&b)[NP
 
 // Writes `cnt` consecutive results starting at Y + off (all in range when
 // full) as FP32 or, for an FP64 output, base + value.
-template <typename TOut>
+template <typename TOut, typename TV>
 __device__ __forceinline__ void store_run(TOut* __restrict__ Y, const double* __restrict__ base, int64_t off,
-                                          const float* v, int cnt, int valid, bool vec) {
+                                          const TV* v, int cnt, int valid, bool vec) {
   if (vec && valid >= cnt) {
     if constexpr (sizeof(TOut) == 4) {
-      for (int e = 0; e < cnt; e += 4) *(f4*)(Y + off + e) = f4{v[e], v[e + 1], v[e + 2], v[e + 3]};
+      for (int e = 0; e < cnt; e += 4)
+        *(f4*)(Y + off + e) = f4{(float)v[e], (float)v[e + 1], (float)v[e + 2], (float)v[e + 3]};
     } else {
       for (int e = 0; e < cnt; e += 2) {
         d2 w = d2{(double)v[e], (double)v[e + 1]};
@@ -103,7 +104,7 @@ __device__ __forceinline__ void store_run(TOut* __restrict__ Y, const double* __
     for (int e = 0; e < cnt; ++e) {
       if (e < valid) {
         if constexpr (sizeof(TOut) == 4) {
-          Y[off + e] = v[e];
+          Y[off + e] = (float)v[e];
         } else {
           double w = (double)v[e];
           if (base) w += base[off + e];
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
   const int64_t b0 = bt * 16 * TN;
   const float* __restrict__ X = (const float*)jb.X[0];
   const float* __restrict__ PT = (const float*)jb.P[0];
-  const float sc = (float)jb.scale[0];
+  const double sc = jb.scale[0];
 
   const float* pa[TM];
 #pragma unroll
@@ -145,11 +146,11 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
     vb[u] = b < nb;
     pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + 4 * g;
   }
-  f4 acc[TM][TN];
+  d4 acc[TM][TN];
 #pragma unroll
   for (int m = 0; m < TM; ++m)
 #pragma unroll
-    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
 
   auto load = [&](int p0, f4* ar, f4* br) {
 #pragma unroll
@@ -171,9 +172,10 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
     f4 an[TM], bn[TN];
     const bool more = p0 + 16 < n;
     if (more) load(p0 + 16, an, bn);
-    // chunk sum from a zero accumulator, then scaled and added on the VALU
-    // (round to nearest): the rounding error of the long sum stays that of
-    // n/16 FP32 adds, which the eta cancellation of the splitting amplifies.
+    // chunk sum (16 values of p) on the matrix cores from a zero
+    // accumulator, then scaled and added in FP64: the long sum is not
+    // rounded to FP32 until the store, so the eta cancellation of the
+    // splitting only amplifies the per-chunk rounding.
 #pragma unroll
     for (int m = 0; m < TM; ++m)
 #pragma unroll
@@ -181,7 +183,7 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
         f4 t4 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) t4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][jj], bx[u][jj], t4, 0, 0, 0);
-        acc[m][u] += sc * t4;
+        acc[m][u] += sc * d4{(double)t4[0], (double)t4[1], (double)t4[2], (double)t4[3]};
       }
     if (more) {
 #pragma unroll
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     if (!vb[u]) continue;
-    float v[4 * TM];
+    double v[4 * TM];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -227,16 +229,16 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
   const int i0 = it * 16 * TN;
   const int64_t arow = a0 + TM * l;
   const bool lane_full = arow + TM <= na;
-  f4 acc[TM][TN];
+  d4 acc[TM][TN];   // FP64: the terms of a split action cancel (eta up to ~19)
 #pragma unroll
   for (int m = 0; m < TM; ++m)
 #pragma unroll
-    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
   const int64_t slab = na * (int64_t)n * b;
   for (int term = 0; term < nterms; ++term) {
     const float* __restrict__ xb = (const float*)jb.X[term] + slab + arow + na * g;
     const float* __restrict__ pbp = (const float*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
-    const float sc = (float)jb.scale[term];
+    const double sc = jb.scale[term];
     // one k-chunk = 4 k-steps (16 values of p): operands of step k in
     // xr[k], pr[k]
     auto load = [&](int p0, float (*xr)[TM], float (*pr)[TN]) {
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
       float xn[4][TM], pn[4][TN];
       const bool more = p0 + 16 < n;
       if (more) load(p0 + 16, xn, pn);
-      // chunk sum from a zero accumulator, scaled and added on the VALU
+      // chunk sum from a zero accumulator, scaled and added in FP64
 #pragma unroll
       for (int m = 0; m < TM; ++m)
 #pragma unroll
@@ -276,7 +278,7 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
           f4 t4 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int k = 0; k < 4; ++k) t4 = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[k][m], pr[k][u], t4, 0, 0, 0);
-          acc[m][u] += sc * t4;
+          acc[m][u] += sc * d4{(double)t4[0], (double)t4[1], (double)t4[2], (double)t4[3]};
         }
       if (more) {
 #pragma unroll
@@ -297,7 +299,7 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
   for (int u = 0; u < TN; ++u) {
     const int i = i0 + TN * l + u;
     if (i >= n) continue;
-    float v[4 * TM];
+    double v[4 * TM];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
