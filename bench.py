@@ -180,6 +180,64 @@ def run_batch(torch, setd, wl, warmup=3, serial_steps=10):
     return res
 
 
+def run_methods(torch, setd, prob, A, u0, f64_step_s, steps=20):
+    """The other two integrators on the same workload and context type:
+    exprk3ds_cplx (two complex Tuckers per split action) and etd2rkds (one
+    Tucker per phi action, second order)."""
+    out = {}
+    for name in ("exprk3ds_cplx", "etd2rkds"):
+        ctx = setd.Context(prob.dims, A, prob.tau)
+        u = u0.clone()
+        fn = ctx.step_cplx if name == "exprk3ds_cplx" else ctx.step2
+        fn(u, 2, prob.g_kind, prob.params)          # set-up and warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(u, steps, prob.g_kind, prob.params)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        out[name] = dict(steps_per_s=round(steps / dt, 3), ms_per_step=round(dt / steps * 1e3, 4),
+                         time_vs_exprk3ds_real=round((dt / steps) / f64_step_s, 3), steps=steps)
+        log("%s: %.2f steps/s" % (name, steps / dt))
+    return out
+
+
+def run_adjoint(torch, setd, wl, nsteps=200, checkpoint=20):
+    """Differentiation form: L = 1/2 ||u(T) - u_target||^2 on 3D FHN 128^3 after
+    200 steps (u_target from eps = 0.55, a1 = 2.1), gradients with respect to
+    u0, (eps, a1, a0) and the diffusion coefficients through the checkpointed
+    adjoint (one checkpoint every 20 steps)."""
+    from paper_2310_07551_amd import autograd as sad
+    p = wl.make("fhn3d_128")
+    dev = torch.device("cuda:0")
+    D = [[torch.from_numpy(wl.neumann_d2(m).ravel(order="F").copy()).to(dev) for m in p.dims] for _ in range(2)]
+    dv = float(p.A[1][0][1, 1] / wl.neumann_d2(p.dims[0])[1, 1])
+    u0 = torch.from_numpy(p.u0_flat()).to(dev)
+    kw = dict(dims=p.dims, D=D, g_kind=p.g_kind, tau=p.tau, nsteps=nsteps, checkpoint=checkpoint)
+    with torch.no_grad():
+        target = sad.integrate(u0, torch.tensor([0.55, 2.1, 0.0], dtype=torch.float64),
+                               torch.tensor([1.0, dv], dtype=torch.float64), **kw).clone()
+    times = []
+    for rep in range(2):                      # the first run includes the set-up of both banks
+        params = torch.tensor(list(p.params[:3]), dtype=torch.float64, requires_grad=True)
+        diff = torch.tensor([1.0, dv], dtype=torch.float64, requires_grad=True)
+        ui = u0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uT = sad.integrate(ui, params, diff, **kw)
+        loss = 0.5 * ((uT - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append((t1 - t0, time.perf_counter() - t1))
+    fwd, bwd = times[-1]
+    log("adjoint: forward %.3f s, backward %.3f s" % (fwd, bwd))
+    return dict(workload="fhn3d_128", steps=nsteps, checkpoint=checkpoint, loss=loss.item(),
+                forward_s=round(fwd, 4), backward_s=round(bwd, 4), backward_over_forward=round(bwd / fwd, 3),
+                grad_eps=params.grad[0].item(), grad_a1=params.grad[1].item(), grad_dv=diff.grad[1].item())
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,9 +248,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of this size (HBM counter calibration) and exit")
-    ap.add_argument("--forms", default="f64,f32,bf16x3,bf16x2,batch",
-                    help="forms to time besides the FP64 metric: f32, bf16x3, bf16x2 (compared against f64) and "
-                         "batch (64 uneven 2D Schnakenberg instances, 100 steps)")
+    ap.add_argument("--forms", default="f64,f32,bf16x3,bf16x2,batch,methods,adjoint",
+                    help="forms to time besides the FP64 metric: f32, bf16x3, bf16x2 (compared against f64), "
+                         "batch (64 uneven 2D Schnakenberg instances, 100 steps), methods (exprk3ds_cplx and "
+                         "etd2rkds on the same workload) and adjoint (gradient of the 3D FHN 128^3, 200-step loss)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -260,6 +319,8 @@ def main():
         log("%s: %.2f steps/s, rel_l2 vs f64 %s" % (name, args.steps / dt_l, forms[name]["rel_l2_vs_f64"]))
 
     batch = run_batch(torch, setd, wl) if "batch" in args.forms.split(",") else None
+    methods = run_methods(torch, setd, prob, A, u0, dt / args.steps) if "methods" in args.forms.split(",") else None
+    adjoint = run_adjoint(torch, setd, wl) if "adjoint" in args.forms.split(",") else None
 
     steps_per_s = args.steps / dt
     nterms = 2 if prob.d == 2 else 3
@@ -309,6 +370,8 @@ def main():
         "kernels": kernels,
         "precision_forms": forms,
         "batch_form": batch,
+        "method_forms": methods,
+        "adjoint_form": adjoint,
         "roofline": roof,
         "cpu_baseline": None,
     }

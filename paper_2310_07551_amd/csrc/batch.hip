@@ -96,7 +96,7 @@ struct setd_batch {
   // before the next launch
   bool params_dirty = true;
   // tile choice: {tm, tn, grid cap} for mode 1 and for modes >= 2
-  int cfg1[3] = {2, 4, 0}, cfgB[3] = {4, 2, 0};
+  int cfg1[3] = {4, 4, 0}, cfgB[3] = {4, 2, 0};
   bool tuned = false;
   // plan of one step for state buffer plan_u
   std::vector<Op> plan;

@@ -180,8 +180,11 @@ __device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
 }
 
 // Job table in the kernel arguments (up to kMaxJobs outputs per launch).
+// Two waves per SIMD is the target occupancy: with that register budget the
+// accumulators stay in place through the k loop (a tighter default made the
+// compiler copy all of them between register files every iteration).
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+__global__ void __launch_bounds__(64, 2) mode1_f64_kernel(const ModeJobs J, int64_t per_xcd) {
   const int64_t t = remap_xcd(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const int j = find_job(J, t);
@@ -192,7 +195,7 @@ __global__ void __launch_bounds__(64) mode1_f64_kernel(const ModeJobs J, int64_t
 // instances): a persistent grid walks the logical tiles with a stride that
 // keeps every block on its XCD's contiguous range.
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) mode1_f64_list_kernel(const ModeJob* __restrict__ jobs,
+__global__ void __launch_bounds__(64, 2) mode1_f64_list_kernel(const ModeJob* __restrict__ jobs,
                                                             const int64_t* __restrict__ begins, int njobs,
                                                             int64_t total, int64_t per_xcd) {
   for (int64_t raw = blockIdx.x; raw < 8 * per_xcd; raw += gridDim.x) {
@@ -480,8 +483,9 @@ void job_work(const ModeJobs& J, int es_in, int es_out, int es_mat, double& flop
 }
 
 int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
-  // default from a sweep on MI355X (FHN 128^3 and 256^3): 2 x 4 tiles
-  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{2, 4});
+  // default from a sweep on MI355X at FHN 256^3 (two waves per SIMD):
+  // 4 x 4 53.7, 2 x 4 43.7, 4 x 2 42.2, 2 x 2 34.3 TFLOP/s
+  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{4, 4});
   finish_tiles(J, true, cfg.tm, cfg.tn);
   if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
