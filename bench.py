@@ -205,15 +205,16 @@ def run_methods(torch, setd, prob, A, u0, f64_step_s, steps=20):
 def run_adjoint(torch, setd, wl, nsteps=200, checkpoint=20):
     """Differentiation form: L = 1/2 ||u(T) - u_target||^2 on 3D FHN 128^3 after
     200 steps (u_target from eps = 0.55, a1 = 2.1), gradients with respect to
-    u0, (eps, a1, a0) and the diffusion coefficients through the checkpointed
-    adjoint (one checkpoint every 20 steps)."""
+    u0, (eps, a1, a0) and d_v through the checkpointed adjoint (one
+    checkpoint every 20 steps)."""
     from paper_2310_07551_amd import autograd as sad
     p = wl.make("fhn3d_128")
     dev = torch.device("cuda:0")
     D = [[torch.from_numpy(wl.neumann_d2(m).ravel(order="F").copy()).to(dev) for m in p.dims] for _ in range(2)]
     dv = float(p.A[1][0][1, 1] / wl.neumann_d2(p.dims[0])[1, 1])
     u0 = torch.from_numpy(p.u0_flat()).to(dev)
-    kw = dict(dims=p.dims, D=D, g_kind=p.g_kind, tau=p.tau, nsteps=nsteps, checkpoint=checkpoint)
+    kw = dict(dims=p.dims, D=D, g_kind=p.g_kind, tau=p.tau, nsteps=nsteps, checkpoint=checkpoint,
+              diff_components=(1,))   # d_v only, as the workload asks
     with torch.no_grad():
         target = sad.integrate(u0, torch.tensor([0.55, 2.1, 0.0], dtype=torch.float64),
                                torch.tensor([1.0, dv], dtype=torch.float64), **kw).clone()

@@ -25,7 +25,7 @@ class _Integrate(_torch().autograd.Function):
     @staticmethod
     def forward(fctx, u0, params, diff, spec):
         torch = _torch()
-        dims, D, g_kind, tau, nsteps, checkpoint = spec
+        dims, D, g_kind, tau, nsteps, checkpoint, diff_components = spec
         ncomp = len(D)
         dvals = [float(x) for x in diff.detach().cpu()]
         pvals = [float(x) for x in params.detach().cpu()]
@@ -48,12 +48,17 @@ class _Integrate(_torch().autograd.Function):
     def backward(fctx, grad_u):
         torch = _torch()
         ctx, checkpoints, pvals, dvals, spec = fctx.setd
-        dims, D, g_kind, tau, nsteps, checkpoint = spec
+        dims, D, g_kind, tau, nsteps, checkpoint, diff_components = spec
         ncomp = len(D)
         ubar = grad_u.detach().to(torch.float64).contiguous().clone()
         grad = torch.zeros(len(pvals) + ncomp, dtype=torch.float64, device=ubar.device)
         work = torch.empty_like(ubar)
-        mask = (1 << ncomp) - 1
+        # diffusion-size gradients only for the components asked for (each
+        # costs 2d extra Tucker groups per step)
+        mask = 0
+        if fctx.needs_input_grad[2]:
+            for c in (range(ncomp) if diff_components is None else diff_components):
+                mask |= 1 << int(c)
         for seg in range(len(checkpoints) - 1, -1, -1):
             k = min(checkpoint, nsteps - seg * checkpoint)
             states = torch.empty((k, ubar.numel()), dtype=torch.float64, device=ubar.device)
@@ -66,20 +71,23 @@ class _Integrate(_torch().autograd.Function):
                 ctx.adjoint_step(states[j], ubar, g_kind, pvals, grad, sigma_mask=mask)
         g = grad.cpu()
         gp = g[:len(pvals)].clone()
-        gd = torch.tensor([g[len(pvals) + c].item() / dvals[c] for c in range(ncomp)], dtype=torch.float64)
+        gd = torch.tensor([g[len(pvals) + c].item() / dvals[c] if (mask >> c) & 1 else 0.0 for c in range(ncomp)],
+                          dtype=torch.float64)
         fctx.setd = None
         ctx.close()
         return ubar, gp.to(fctx.devices[0]), gd.to(fctx.devices[1]), None
 
 
 def integrate(u0, params, diff, *, dims: Sequence[int], D, g_kind: int, tau: float, nsteps: int,
-              checkpoint: int = 20):
+              checkpoint: int = 20, diff_components=None):
     """u(T) after nsteps split-ETD3 steps from u0 (flat FP64 device tensor,
     component-major), differentiable in u0, params (1-D tensor of reaction
     parameters) and diff (1-D tensor, one diffusion coefficient per
     component; A_mu^(c) = diff[c] * D[c][mu], D column-major FP64 device
-    matrices)."""
+    matrices).  diff_components: the components whose diffusion gradient is
+    wanted (default all; the others get 0)."""
     if checkpoint < 1:
         raise ValueError("checkpoint must be >= 1")
-    spec = (tuple(int(x) for x in dims), D, int(g_kind), float(tau), int(nsteps), int(checkpoint))
+    comps = None if diff_components is None else tuple(int(c) for c in diff_components)
+    spec = (tuple(int(x) for x in dims), D, int(g_kind), float(tau), int(nsteps), int(checkpoint), comps)
     return _Integrate.apply(u0, params, diff, spec)
