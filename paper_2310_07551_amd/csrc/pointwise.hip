@@ -9,6 +9,8 @@
 //  * deterministic norms (fixed-order two-pass reductions).
 // All of these are bound by HBM bandwidth: one thread per grid point,
 // contiguous along i_1, no reuse beyond the stencil neighbours.
+#include <algorithm>
+
 #include "common.hpp"
 #include "pointwise.hpp"
 
@@ -155,13 +157,9 @@ __device__ __forceinline__ void reaction(const GParams& P, double u, double v, d
 // Per-point bodies.  u holds ncomp fields, component c at u + c * cs;
 // point idx has grid indices (i1, i2, i3) with i1 fastest.
 template <typename TF>
-__device__ __forceinline__ void gf_point(const double* __restrict__ u, int64_t cs, int64_t idx, int ncomp, int d,
-                                         int n1, int n2, int n3, const StencilSet& S, const GParams& gp,
-                                         double* __restrict__ G, TF* __restrict__ F) {
-  const int i1 = (int)(idx % n1);
-  const int64_t r = idx / n1;
-  const int i2 = (int)(r % n2);
-  const int i3 = (d == 3) ? (int)(r / n2) : 0;
+__device__ __forceinline__ void gf_point_at(const double* __restrict__ u, int64_t cs, int64_t idx, int i1, int i2,
+                                            int i3, int ncomp, int d, int n1, int n2, int n3, const StencilSet& S,
+                                            const GParams& gp, double* __restrict__ G, TF* __restrict__ F) {
   const int idxs[3] = {i1, i2, i3};
   const int ns[3] = {n1, n2, n3};
   const int64_t strides[3] = {1, (int64_t)n1, (int64_t)n1 * n2};
@@ -186,6 +184,18 @@ __device__ __forceinline__ void gf_point(const double* __restrict__ u, int64_t c
   }
 }
 
+// Same, for a flat point index (the batched kernels).
+template <typename TF>
+__device__ __forceinline__ void gf_point(const double* __restrict__ u, int64_t cs, int64_t idx, int ncomp, int d,
+                                         int n1, int n2, int n3, const StencilSet& S, const GParams& gp,
+                                         double* __restrict__ G, TF* __restrict__ F) {
+  const int i1 = (int)(idx % n1);
+  const int64_t r = idx / n1;
+  const int i2 = (int)(r % n2);
+  const int i3 = (d == 3) ? (int)(r / n2) : 0;
+  gf_point_at<TF>(u, cs, idx, i1, i2, i3, ncomp, d, n1, n2, n3, S, gp, G, F);
+}
+
 __device__ __forceinline__ void g_point(const double* __restrict__ u, int64_t cs, int64_t idx, int ncomp,
                                         const GParams& gp, double* __restrict__ G) {
   double g[2];
@@ -204,12 +214,16 @@ __device__ __forceinline__ void stage_d_point(const double* __restrict__ Us, con
 
 // One thread per grid point.  Writes G_c = g_c(u) and F_c = (K_c u_c) + G_c
 // for every component (F in FP64, or FP32 for the reduced-precision Tuckers).
+// The grid is (ceil(n1 / blockDim.x), n2, n3): the grid indices come from
+// the block coordinates, with no integer division per point.
 template <typename TF>
 __global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64_t N, int d, int n1, int n2,
                                   int n3, StencilSet S, GParams gp, double* __restrict__ G, TF* __restrict__ F) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N) return;
-  gf_point<TF>(u, N, idx, ncomp, d, n1, n2, n3, S, gp, G, F);
+  const int i1 = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i1 >= n1) return;
+  const int i2 = (int)blockIdx.y, i3 = (int)blockIdx.z;
+  const int64_t idx = ((int64_t)i3 * n2 + i2) * n1 + i1;
+  gf_point_at<TF>(u, N, idx, i1, i2, i3, ncomp, d, n1, n2, n3, S, gp, G, F);
 }
 
 // G_c = g_c(u) only (the dense-K path adds the mode products afterwards).
@@ -272,14 +286,15 @@ int launch_batch_pointwise(int kind, const BatchInstDev* inst, const int64_t* bl
 int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* dims, const StencilSet& S,
                       const GParams& gp, double* G, void* F, DType ftype, hipStream_t s) {
   const int n3 = d == 3 ? dims[2] : 1;
-  const dim3 grid((unsigned)ceil_div(N, 256));
+  const int bx = (int)std::min<int64_t>(256, round_up(dims[0], 64));
+  const dim3 grid((unsigned)ceil_div(dims[0], bx), (unsigned)dims[1], (unsigned)n3);
   // reads u once, writes G (FP64) and F
   ProfScope prof(s, kProfPointwise, 0.0, (double)N * ncomp * (8 + 8 + (ftype == DType::F64 ? 8 : 4)));
   if (ftype == DType::F64)
-    hipLaunchKernelGGL(gf_stencil_kernel<double>, grid, dim3(256), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S,
+    hipLaunchKernelGGL(gf_stencil_kernel<double>, grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S,
                        gp, G, (double*)F);
   else
-    hipLaunchKernelGGL(gf_stencil_kernel<float>, grid, dim3(256), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S, gp,
+    hipLaunchKernelGGL(gf_stencil_kernel<float>, grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S, gp,
                        G, (float*)F);
   SETD_LAUNCHED();
   return SETD_OK;
