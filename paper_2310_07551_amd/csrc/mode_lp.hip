@@ -25,6 +25,8 @@
 // modes >= 2:  MFMA rows = a (contiguous tensor index), columns = i, k = p;
 //   the FP32 form reads the matrix column-major packed, the bf16 form
 //   row-major packed (it needs 8 consecutive p of one row per lane).
+#include <cstring>
+
 #include "common.hpp"
 
 #include <cstdlib>
@@ -116,10 +118,18 @@ __device__ __forceinline__ void store_run(TOut* __restrict__ Y, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// FP32, mode 1
+// FP32 with the accumulation chained on the matrix cores (the layout and
+// load scheme of the FP64 kernels: lanes load 4 consecutive p, an interior
+// variant without masks in ping-pong registers).  FP32 MFMA accumulator
+// layout (probed): lane (g, l) register r holds D[4 g + r][l].
 // ---------------------------------------------------------------------------
-template <int TM, int TN, bool VEC, typename TOut>
-__global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t per_xcd) {
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int TM, int TN, int MODE, typename TOut>
+__global__ void __launch_bounds__(64, 2) mode1_f32c_kernel(const ModeJobs J, int64_t per_xcd) {
+  constexpr bool VEC = MODE >= 1;
   const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const ModeJob& jb = J.job[find_job_lp(J, t)];
@@ -133,8 +143,7 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
   const int64_t b0 = bt * 16 * TN;
   const float* __restrict__ X = (const float*)jb.X[0];
   const float* __restrict__ PT = (const float*)jb.P[0];
-  const double sc = jb.scale[0];
-
+  const float sc = (float)jb.scale[0];
   const float* pa[TM];
 #pragma unroll
   for (int m = 0; m < TM; ++m) pa[m] = PT + (int64_t)(i0 + TM * l + m) * ldp + 4 * g;
@@ -146,74 +155,84 @@ __global__ void __launch_bounds__(64) mode1_f32_kernel(const ModeJobs J, int64_t
     vb[u] = b < nb;
     pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + 4 * g;
   }
-  d4 acc[TM][TN];
+  f4 acc[TM][TN];
 #pragma unroll
   for (int m = 0; m < TM; ++m)
 #pragma unroll
-    for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
-
-  auto load = [&](int p0, f4* ar, f4* br) {
+    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
+  auto mma = [&](const f4* ar, const f4* br) {
 #pragma unroll
-    for (int m = 0; m < TM; ++m) ar[m] = *(const f4*)(pa[m] + p0);
-    const bool full = VEC && (p0 + 16 <= n);
+    for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-    for (int u = 0; u < TN; ++u) {
-      if (full) {
-        br[u] = vb[u] ? *(const f4*)(pb[u] + p0) : f4{0.f, 0.f, 0.f, 0.f};
-      } else {
+      for (int m = 0; m < TM; ++m)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] : 0.f;
-      }
-    }
+        for (int u = 0; u < TN; ++u) acc[m][u] = mfma32(ar[m][jj], br[u][jj], acc[m][u]);
   };
-  f4 a[TM], bx[TN];
-  load(0, a, bx);
-  for (int p0 = 0; p0 < n; p0 += 16) {
-    f4 an[TM], bn[TN];
-    const bool more = p0 + 16 < n;
-    if (more) load(p0 + 16, an, bn);
-    // chunk sum (16 values of p) on the matrix cores from a zero
-    // accumulator, then scaled and added in FP64: the long sum is not
-    // rounded to FP32 until the store, so the eta cancellation of the
-    // splitting only amplifies the per-chunk rounding.
+  if constexpr (MODE == 2) {
+    auto load = [&](int p0, f4* ar, f4* br) {
 #pragma unroll
-    for (int m = 0; m < TM; ++m)
+      for (int m = 0; m < TM; ++m) ar[m] = *(const f4*)(pa[m] + p0);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) br[u] = *(const f4*)(pb[u] + p0);
+    };
+    f4 a0[TM], b0r[TN], a1[TM], b1r[TN];
+    load(0, a0, b0r);
+    for (int p0 = 0; p0 < n; p0 += 32) {
+      load(p0 + 16, a1, b1r);
+      mma(a0, b0r);
+      load(p0 + 32 < n ? p0 + 32 : p0, a0, b0r);
+      mma(a1, b1r);
+    }
+  } else {
+    auto load = [&](int p0, f4* ar, f4* br) {
+#pragma unroll
+      for (int m = 0; m < TM; ++m) ar[m] = *(const f4*)(pa[m] + p0);
+      const bool full = VEC && (p0 + 16 <= n);
 #pragma unroll
       for (int u = 0; u < TN; ++u) {
-        f4 t4 = f4{0.f, 0.f, 0.f, 0.f};
+        if (full) {
+          br[u] = vb[u] ? *(const f4*)(pb[u] + p0) : f4{0.f, 0.f, 0.f, 0.f};
+        } else {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) t4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][jj], bx[u][jj], t4, 0, 0, 0);
-        acc[m][u] += sc * d4{(double)t4[0], (double)t4[1], (double)t4[2], (double)t4[3]};
+          for (int e = 0; e < 4; ++e) br[u][e] = (vb[u] && p0 + 4 * g + e < n) ? pb[u][p0 + e] : 0.f;
+        }
       }
-    if (more) {
+    };
+    f4 a[TM], bx[TN];
+    load(0, a, bx);
+    for (int p0 = 0; p0 < n; p0 += 16) {
+      f4 an[TM], bn[TN];
+      const bool more = p0 + 16 < n;
+      if (more) load(p0 + 16, an, bn);
+      mma(a, bx);
+      if (more) {
 #pragma unroll
-      for (int m = 0; m < TM; ++m) a[m] = an[m];
+        for (int m = 0; m < TM; ++m) a[m] = an[m];
 #pragma unroll
-      for (int u = 0; u < TN; ++u) bx[u] = bn[u];
+        for (int u = 0; u < TN; ++u) bx[u] = bn[u];
+      }
     }
   }
-  // tile row q = 4 g + r -> output row i0 + TM q + m: lane (g, l) owns the
-  // 4 TM consecutive rows i0 + 4 TM g + (TM r + m) of column b0 + 16 u + l.
+  // lane (g, l) owns the 4 TM consecutive rows i0 + 4 TM g + (TM r + m) of
+  // column b0 + 16 u + l
   TOut* __restrict__ Y = (TOut*)jb.Y;
   const double* __restrict__ base = (const double*)jb.base;
   const int ir = i0 + 4 * TM * g;
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     if (!vb[u]) continue;
-    double v[4 * TM];
+    float v[4 * TM];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int m = 0; m < TM; ++m) v[TM * r + m] = acc[m][u][r];
+      for (int m = 0; m < TM; ++m) v[TM * r + m] = sc * acc[m][u][r];
     store_run<TOut>(Y, base, (b0 + 16 * u + l) * (int64_t)n + ir, v, 4 * TM, n - ir, VEC);
   }
 }
 
-// ---------------------------------------------------------------------------
-// FP32, modes >= 2
-// ---------------------------------------------------------------------------
-template <int TM, int TN, bool VEC, typename TOut>
-__global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t per_xcd) {
+template <int TM, int TN, int MODE, typename TOut>
+__global__ void __launch_bounds__(64, 2) modeB_f32c_kernel(const ModeJobs J, int64_t per_xcd) {
+  constexpr bool VEC = MODE >= 1;
   const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const ModeJob& jb = J.job[find_job_lp(J, t)];
@@ -229,69 +248,101 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
   const int i0 = it * 16 * TN;
   const int64_t arow = a0 + TM * l;
   const bool lane_full = arow + TM <= na;
-  d4 acc[TM][TN];   // FP64: the terms of a split action cancel (eta up to ~19)
+  f4 acc[TM][TN];
 #pragma unroll
   for (int m = 0; m < TM; ++m)
 #pragma unroll
-    for (int u = 0; u < TN; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < TN; ++u) acc[m][u] = f4{0.f, 0.f, 0.f, 0.f};
   const int64_t slab = na * (int64_t)n * b;
   for (int term = 0; term < nterms; ++term) {
     const float* __restrict__ xb = (const float*)jb.X[term] + slab + arow + na * g;
     const float* __restrict__ pbp = (const float*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
-    const double sc = jb.scale[term];
-    // one k-chunk = 4 k-steps (16 values of p): operands of step k in
-    // xr[k], pr[k]
-    auto load = [&](int p0, float (*xr)[TM], float (*pr)[TN]) {
+    const float sc = (float)jb.scale[term];
+    constexpr int KB = 4;   // k-steps per chunk
+    auto mmablk = [&](float (*xr)[TM], float (*pr)[TN]) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int p = p0 + 4 * k;
-        const bool vp = p + g < n;
-        const float* xs = xb + na * (int64_t)p;
-        if (VEC && TM == 4 && lane_full && vp) {
-          const f4 v = *(const f4*)xs;
-#pragma unroll
-          for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
-        } else if (VEC && TM == 2 && lane_full && vp) {
-          const f2 v = *(const f2*)xs;
-#pragma unroll
-          for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
-        } else {
-#pragma unroll
-          for (int m = 0; m < TM; ++m) xr[k][m] = (vp && arow + m < na) ? xs[m] : 0.f;
-        }
-        const float* ps = pbp + (int64_t)ldp * p;   // padded: always in range
-#pragma unroll
-        for (int u = 0; u < TN; ++u) pr[k][u] = ps[u];
-      }
-    };
-    float xr[4][TM], pr[4][TN];
-    load(0, xr, pr);
-    for (int p0 = 0; p0 < n; p0 += 16) {
-      float xn[4][TM], pn[4][TN];
-      const bool more = p0 + 16 < n;
-      if (more) load(p0 + 16, xn, pn);
-      // chunk sum from a zero accumulator, scaled and added in FP64
-#pragma unroll
-      for (int m = 0; m < TM; ++m)
+      for (int k = 0; k < KB; ++k)
 #pragma unroll
         for (int u = 0; u < TN; ++u) {
-          f4 t4 = f4{0.f, 0.f, 0.f, 0.f};
+          const float pv = pr[k][u] * sc;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) t4 = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[k][m], pr[k][u], t4, 0, 0, 0);
-          acc[m][u] += sc * d4{(double)t4[0], (double)t4[1], (double)t4[2], (double)t4[3]};
+          for (int m = 0; m < TM; ++m) acc[m][u] = mfma32(xr[k][m], pv, acc[m][u]);
         }
-      if (more) {
+    };
+    auto loadblk = [&](int p0, float (*xr)[TM], float (*pr)[TN]) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < KB; ++k) {
+        const int p = p0 + 4 * k;
+        const float* xs = xb + na * (int64_t)p;
+        const float* ps = pbp + (int64_t)ldp * p;   // padded: always in range
+        if constexpr (MODE == 2) {
+          if constexpr (TM == 4) {
+            const f4 v = *(const f4*)xs;
 #pragma unroll
-          for (int m = 0; m < TM; ++m) xr[k][m] = xn[k][m];
+            for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+          } else {
+            const f2 v = *(const f2*)xs;
 #pragma unroll
-          for (int u = 0; u < TN; ++u) pr[k][u] = pn[k][u];
+            for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+          }
+        } else {
+          const bool vp = p + g < n;
+          if (VEC && TM == 4 && lane_full && vp) {
+            const f4 v = *(const f4*)xs;
+#pragma unroll
+            for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+          } else if (VEC && TM == 2 && lane_full && vp) {
+            const f2 v = *(const f2*)xs;
+#pragma unroll
+            for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
+          } else {
+#pragma unroll
+            for (int m = 0; m < TM; ++m) xr[k][m] = (vp && arow + m < na) ? xs[m] : 0.f;
+          }
+        }
+        if constexpr (TN == 2) {
+          const f2 w = *(const f2*)ps;
+          pr[k][0] = w[0];
+          pr[k][1] = w[1];
+        } else if constexpr (TN == 4) {
+          const f4 w = *(const f4*)ps;
+#pragma unroll
+          for (int u = 0; u < TN; ++u) pr[k][u] = w[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < TN; ++u) pr[k][u] = ps[u];
+        }
+      }
+    };
+    if constexpr (MODE == 2) {
+      float x0[KB][TM], q0[KB][TN], x1[KB][TM], q1[KB][TN];
+      loadblk(0, x0, q0);
+      for (int p0 = 0; p0 < n; p0 += 8 * KB) {
+        loadblk(p0 + 4 * KB, x1, q1);
+        mmablk(x0, q0);
+        loadblk(p0 + 8 * KB < n ? p0 + 8 * KB : p0, x0, q0);
+        mmablk(x1, q1);
+      }
+    } else {
+      float xr[KB][TM], pr[KB][TN];
+      loadblk(0, xr, pr);
+      for (int p0 = 0; p0 < n; p0 += 4 * KB) {
+        float xn[KB][TM], pn[KB][TN];
+        const bool more = p0 + 4 * KB < n;
+        if (more) loadblk(p0 + 4 * KB, xn, pn);
+        mmablk(xr, pr);
+        if (more) {
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+#pragma unroll
+            for (int m = 0; m < TM; ++m) xr[k][m] = xn[k][m];
+#pragma unroll
+            for (int u = 0; u < TN; ++u) pr[k][u] = pn[k][u];
+          }
         }
       }
     }
   }
-  // lane (g, l) owns a = a0 + 4 TM g + (TM r + m) of column i0 + TN l + u
   TOut* __restrict__ Y = (TOut*)jb.Y;
   const double* __restrict__ base = (const double*)jb.base;
   const int64_t ar = a0 + 4 * TM * g;
@@ -299,7 +350,7 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
   for (int u = 0; u < TN; ++u) {
     const int i = i0 + TN * l + u;
     if (i >= n) continue;
-    double v[4 * TM];
+    float v[4 * TM];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -309,8 +360,6 @@ __global__ void __launch_bounds__(64) modeB_f32_kernel(const ModeJobs J, int64_t
   }
 }
 
-// ---------------------------------------------------------------------------
-// BF16x3, mode 1: k-chunks of 32; lane group g holds p0 + 8 g + (0..7)
 // ---------------------------------------------------------------------------
 template <int NP, int TM, int TN, bool VEC, typename TOut>
 __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_t per_xcd) {
@@ -504,9 +553,7 @@ namespace {
 
 template <bool VEC, typename T>
 void go_mode1(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
-  if (prec == SETD_PREC_F32)
-    hipLaunchKernelGGL((mode1_f32_kernel<kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
-  else if (prec == SETD_PREC_BF16X3)
+  if (prec == SETD_PREC_BF16X3)
     hipLaunchKernelGGL((mode1_bf16_kernel<3, kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
   else
     hipLaunchKernelGGL((mode1_bf16_kernel<2, kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
@@ -514,9 +561,7 @@ void go_mode1(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per
 
 template <bool VEC, typename T>
 void go_modeB(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
-  if (prec == SETD_PREC_F32)
-    hipLaunchKernelGGL((modeB_f32_kernel<kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
-  else if (prec == SETD_PREC_BF16X3)
+  if (prec == SETD_PREC_BF16X3)
     hipLaunchKernelGGL((modeB_bf16_kernel<3, kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
   else
     hipLaunchKernelGGL((modeB_bf16_kernel<2, kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
@@ -524,7 +569,97 @@ void go_modeB(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per
 
 }  // namespace
 
+namespace {
+
+// FP32 tile shapes: defaults from a sweep at 3D FHN 256^3 (mode 1 4 x 4,
+// modes >= 2 4 x 4: 96 TFLOP/s; 4 x 2 / 4 x 2: 90), overridable with
+// SETD_TILE_F32_MODE1 / SETD_TILE_F32_MODEB ("4x2" etc.).
+void f32_tile(const char* name, int& tm, int& tn) {
+  const char* e = std::getenv(name);
+  int a = 0, b = 0;
+  if (e && std::sscanf(e, "%dx%d", &a, &b) == 2 && (a == 2 || a == 4) && (b == 2 || b == 4)) {
+    tm = a;
+    tn = b;
+  }
+}
+
+#define SETD_F32C(KERNEL, TM_, TN_)                                                                  \
+  if (tm == TM_ && tn == TN_) {                                                                     \
+    if (mode == 2)                                                                                  \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 2, T>), grid, dim3(64), 0, s, J, per);                    \
+    else if (mode == 1)                                                                             \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 1, T>), grid, dim3(64), 0, s, J, per);                    \
+    else                                                                                            \
+      hipLaunchKernelGGL((KERNEL<TM_, TN_, 0, T>), grid, dim3(64), 0, s, J, per);                    \
+    return;                                                                                         \
+  }
+
+template <typename T>
+void go_mode1_f32c(int tm, int tn, int mode, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  SETD_F32C(mode1_f32c_kernel, 4, 4)
+  SETD_F32C(mode1_f32c_kernel, 4, 2)
+  SETD_F32C(mode1_f32c_kernel, 2, 4)
+  SETD_F32C(mode1_f32c_kernel, 2, 2)
+}
+template <typename T>
+void go_modeB_f32c(int tm, int tn, int mode, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  SETD_F32C(modeB_f32c_kernel, 4, 4)
+  SETD_F32C(modeB_f32c_kernel, 4, 2)
+  SETD_F32C(modeB_f32c_kernel, 2, 4)
+  SETD_F32C(modeB_f32c_kernel, 2, 2)
+}
+
+int launch_mode1_f32c(ModeJobs& J, DType out, hipStream_t s) {
+  int tm = 4, tn = 4;
+  f32_tile("SETD_TILE_F32_MODE1", tm, tn);
+  finish_tiles_lp(J, true, tm, tn);
+  if (J.total_tiles == 0) return SETD_OK;
+  bool vec = true, interior = true;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    vec = vec && (jb.n % 4 == 0) && aligned_lp(jb.X[0], 16) && aligned_lp(jb.Y, 16) && aligned_lp(jb.base, 16);
+    interior = interior && jb.n % 32 == 0 && jb.nb % (16 * tn) == 0;
+  }
+  const int mode = vec ? (interior ? 2 : 1) : 0;
+  double fl = 0.0, by = 0.0;
+  if (prof_on()) job_work(J, 4, out == DType::F64 ? 8 : 4, 4, fl, by);
+  ProfScope prof(s, kProfMode1LP, fl, by);
+  const int64_t per = ceil_div(J.total_tiles, 8);
+  const dim3 grid((unsigned)(per * 8));
+  if (out == DType::F32) go_mode1_f32c<float>(tm, tn, mode, grid, s, J, per);
+  else go_mode1_f32c<double>(tm, tn, mode, grid, s, J, per);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+int launch_modeB_f32c(ModeJobs& J, DType out, hipStream_t s) {
+  int tm = 4, tn = 4;
+  f32_tile("SETD_TILE_F32_MODEB", tm, tn);
+  finish_tiles_lp(J, false, tm, tn);
+  if (J.total_tiles == 0) return SETD_OK;
+  bool vec = true, interior = true;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    vec = vec && (jb.na % 4 == 0) && aligned_lp(jb.Y, 16) && aligned_lp(jb.base, 16);
+    for (int t = 0; t < jb.nterms; ++t) vec = vec && aligned_lp(jb.X[t], 16);
+    interior = interior && jb.n % 32 == 0 && jb.na % (16 * tm) == 0;
+  }
+  const int mode = vec ? (interior ? 2 : 1) : 0;
+  double fl = 0.0, by = 0.0;
+  if (prof_on()) job_work(J, 4, out == DType::F64 ? 8 : 4, 4, fl, by);
+  ProfScope prof(s, kProfModeBLP, fl, by);
+  const int64_t per = ceil_div(J.total_tiles, 8);
+  const dim3 grid((unsigned)(per * 8));
+  if (out == DType::F32) go_modeB_f32c<float>(tm, tn, mode, grid, s, J, per);
+  else go_modeB_f32c<double>(tm, tn, mode, grid, s, J, per);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+}  // namespace
+
 int launch_mode1_lp(ModeJobs& J, int prec, DType out, hipStream_t s) {
+  if (prec == SETD_PREC_F32) return launch_mode1_f32c(J, out, s);
   finish_tiles_lp(J, true, kTM1, kTN1);
   if (J.total_tiles == 0) return SETD_OK;
   const int kc = prec == SETD_PREC_F32 ? 4 : 8;     // contiguous p per lane
@@ -547,6 +682,7 @@ int launch_mode1_lp(ModeJobs& J, int prec, DType out, hipStream_t s) {
 }
 
 int launch_modeB_lp(ModeJobs& J, int prec, DType out, hipStream_t s) {
+  if (prec == SETD_PREC_F32) return launch_modeB_f32c(J, out, s);
   finish_tiles_lp(J, false, kTMB, kTNB);
   if (J.total_tiles == 0) return SETD_OK;
   bool vec = true;
