@@ -65,16 +65,20 @@ __device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
   const double* __restrict__ PT = (const double*)jb.P[0];
   const double sc = jb.scale[0];
 
+  // Lanes of group g hold KP consecutive p of each chunk of 4 KP (KP = 2 on
+  // the interior path, whose two-deep register ring must fit beside the
+  // accumulators in the two-wave budget; 4 elsewhere).
+  constexpr int KP = MODE == 2 ? 2 : 4;
   const double* pa[TM];
 #pragma unroll
-  for (int m = 0; m < TM; ++m) pa[m] = PT + (int64_t)(i0 + TM * l + m) * ldp + 4 * g;
+  for (int m = 0; m < TM; ++m) pa[m] = PT + (int64_t)(i0 + TM * l + m) * ldp + KP * g;
   const double* pb[TN];
   bool vb[TN];
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     const int64_t b = b0 + 16 * u + l;
     vb[u] = b < nb;
-    pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + 4 * g;
+    pb[u] = X + (vb[u] ? b : 0) * (int64_t)n + KP * g;
   }
 
   d4 acc[TM][TN];
@@ -96,22 +100,32 @@ __device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
       }
   };
   if constexpr (MODE == 2) {
-    // Interior tile: two k-chunks per iteration in ping-pong registers, no
-    // masks and no register copies.  The last iteration re-reads a valid
-    // chunk instead of branching.
-    auto load = [&](int p0, d4* ar, d4* br) {
+    // Interior tile: chunks of 8 p (two k-steps) in a two-deep register ring,
+    // no masks and no register copies; each chunk is loaded a whole chunk of
+    // MFMAs before its use.  The last loads re-read a valid chunk instead of
+    // branching.
+    auto load = [&](int p0, d2* ar, d2* br) {
 #pragma unroll
-      for (int m = 0; m < TM; ++m) ar[m] = *(const d4*)(pa[m] + p0);
+      for (int m = 0; m < TM; ++m) ar[m] = *(const d2*)(pa[m] + p0);
 #pragma unroll
-      for (int u = 0; u < TN; ++u) br[u] = *(const d4*)(pb[u] + p0);
+      for (int u = 0; u < TN; ++u) br[u] = *(const d2*)(pb[u] + p0);
     };
-    d4 a0[TM], b0r[TN], a1[TM], b1r[TN];
+    auto mma2 = [&](const d2* ar, const d2* br) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+          for (int u = 0; u < TN; ++u) acc[m][u] = mfma(ar[m][jj], br[u][jj], acc[m][u]);
+    };
+    d2 a0[TM], b0r[TN], a1[TM], b1r[TN];
     load(0, a0, b0r);
-    for (int p0 = 0; p0 < n; p0 += 32) {
-      load(p0 + 16, a1, b1r);
-      mma(a0, b0r);
-      load(p0 + 32 < n ? p0 + 32 : p0, a0, b0r);
-      mma(a1, b1r);
+    load(8, a1, b1r);
+    for (int p0 = 0; p0 < n; p0 += 16) {
+      mma2(a0, b0r);
+      load(p0 + 16 < n ? p0 + 16 : p0, a0, b0r);
+      mma2(a1, b1r);
+      load(p0 + 24 < n ? p0 + 24 : p0 + 8, a1, b1r);
     }
   } else {
     auto load = [&](int p0, d4* ar, d4* br) {
@@ -149,6 +163,8 @@ __device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
   // r of lane (g, l), column l; tile row q of row-tile m is output row
   // i0 + TM q + m.  So lane (g, l) owns, for each r, the TM consecutive rows
   // i0 + TM g + 4 TM r + (0..TM-1) of column b0 + 16 u + l.
+  // The interior path leaves the scale to the epilogue.
+  const double osc = MODE == 2 ? sc : 1.0;
   double* __restrict__ Y = (double*)jb.Y;
   const double* __restrict__ base = (const double*)jb.base;
 #pragma unroll
@@ -161,7 +177,7 @@ __device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
       if (VEC && ir + TM <= n) {
 #pragma unroll
         for (int m = 0; m < TM; m += 2) {
-          d2 w = d2{acc[m][u][r], acc[m + 1][u][r]};
+          d2 w = d2{acc[m][u][r], acc[m + 1][u][r]} * osc;
           if (base) w += *(const d2*)(base + col + ir + m);
           *(d2*)(Y + col + ir + m) = w;
         }
@@ -169,7 +185,7 @@ __device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
 #pragma unroll
         for (int m = 0; m < TM; ++m) {
           if (ir + m < n) {
-            double w = acc[m][u][r];
+            double w = acc[m][u][r] * osc;
             if (base) w += base[col + ir + m];
             Y[col + ir + m] = w;
           }
