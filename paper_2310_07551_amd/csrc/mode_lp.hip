@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(64, 2) modeB_f32c_kernel(const ModeJobs J, int
             const f4 v = *(const f4*)xs;
 #pragma unroll
             for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
-          } else if (VEC && TM == 2 && lane_full && vp) {
+          } else if (VEC && TM == 2 && (MODE == 2 || (lane_full && vp))) {
             const f2 v = *(const f2*)xs;
 #pragma unroll
             for (int m = 0; m < TM; ++m) xr[k][m] = v[m];
@@ -361,8 +361,10 @@ __global__ void __launch_bounds__(64, 2) modeB_f32c_kernel(const ModeJobs J, int
 }
 
 // ---------------------------------------------------------------------------
-template <int NP, int TM, int TN, bool VEC, typename TOut>
+// MODE as for the modes >= 2 kernel (2: n % 32 == 0, nb % (16 TN) == 0).
+template <int NP, int TM, int TN, int MODE, typename TOut>
 __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_t per_xcd) {
+  constexpr bool VEC = MODE >= 1;
   const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const ModeJob& jb = J.job[find_job_lp(J, t)];
@@ -396,29 +398,47 @@ __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[m][u] = accs[m][u] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int p0 = 0; p0 < n; p0 += 32) {
-    bf8 ap[TM][NP], bp[TN][NP];
+  // One chunk = 32 p: the matrix pieces and the tensor operand's 8 p values
+  // per lane in FP32; chunks alternate between two register sets so that
+  // each is loaded one chunk of MFMAs before use.
+  auto ldc = [&](int p0, bf8 (&ap)[TM][NP], f8 (&xr)[TN]) {
 #pragma unroll
     for (int m = 0; m < TM; ++m)
 #pragma unroll
       for (int k = 0; k < NP; ++k) ap[m][k] = *(const bf8*)(PH + k * plane + poff[m] + p0);
-    const bool full = VEC && (p0 + 32 <= n);
+    const bool full = MODE == 2 || (VEC && (p0 + 32 <= n));
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
-      f8 x;
-      if (full && vb[u]) {
-        x = *(const f8*)(pb[u] + p0);
+      if (MODE == 2 || (full && vb[u])) {
+        xr[u] = *(const f8*)(pb[u] + p0);
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = (vb[u] && p0 + 8 * g + e < n) ? pb[u][p0 + e] : 0.f;
+        for (int e = 0; e < 8; ++e) xr[u][e] = (vb[u] && p0 + 8 * g + e < n) ? pb[u][p0 + e] : 0.f;
       }
-      split_bf16<NP>(x, bp[u]);
     }
+  };
+  auto cmp = [&](const bf8 (&ap)[TM][NP], const f8 (&xr)[TN]) {
+    bf8 bp[TN][NP];
+#pragma unroll
+    for (int u = 0; u < TN; ++u) split_bf16<NP>(xr[u], bp[u]);
 #pragma unroll
     for (int m = 0; m < TM; ++m)
 #pragma unroll
       for (int u = 0; u < TN; ++u) mfma_split<NP>(ap[m], bp[u], sc, acc[m][u], accs[m][u]);
+  };
+  bf8 a0[TM][NP], a1[TM][NP];
+  f8 x0[TN], x1[TN];
+  ldc(0, a0, x0);
+  int p0 = 0;
+  for (; p0 + 32 < n; p0 += 64) {
+    ldc(p0 + 32, a1, x1);
+    __builtin_amdgcn_sched_barrier(0);
+    cmp(a0, x0);
+    ldc(p0 + 64 < n ? p0 + 64 : p0, a0, x0);   // the last one re-reads a valid chunk
+    __builtin_amdgcn_sched_barrier(0);
+    cmp(a1, x1);
   }
+  if (p0 < n) cmp(a0, x0);
   TOut* __restrict__ Y = (TOut*)jb.Y;
   const double* __restrict__ base = (const double*)jb.base;
   const int ir = i0 + 4 * TM * g;
@@ -437,8 +457,11 @@ __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_
 // ---------------------------------------------------------------------------
 // BF16x3, modes >= 2
 // ---------------------------------------------------------------------------
-template <int NP, int TM, int TN, bool VEC, typename TOut>
+// MODE 0: masked element loads; 1: vector loads; 2: additionally every tile
+// interior and n % 32 == 0 (no masks in the k loop).
+template <int NP, int TM, int TN, int MODE, typename TOut>
 __global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_t per_xcd) {
+  constexpr bool VEC = MODE >= 1;
   const int64_t t = remap_xcd_lp(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const ModeJob& jb = J.job[find_job_lp(J, t)];
@@ -476,19 +499,20 @@ __global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_
 #pragma unroll
         for (int u = 0; u < TN; ++u) accs[m][u] = f4{0.f, 0.f, 0.f, 0.f};
     }
-    for (int p0 = 0; p0 < n; p0 += 32) {
-      // tensor operand: 8 p values (8 g + j) x TM rows per lane
-      f8 xm[TM];
+    // One chunk = 32 p: the tensor operand's 8 p values (8 g + j) x TM rows
+    // per lane in FP32 and the matrix pieces; chunks alternate between two
+    // register sets so that each is loaded one chunk of MFMAs before use.
+    auto ldc = [&](int p0, f8 (&xm)[TM], bf8 (&bp)[TN][NP]) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int p = p0 + 8 * g + j;
-        const bool vp = p < n;
+        const bool vp = MODE == 2 || p < n;
         const float* xs = xb + na * (int64_t)p;
-        if (VEC && TM == 4 && lane_full && vp) {
+        if (VEC && TM == 4 && (MODE == 2 || (lane_full && vp))) {
           const f4 v = *(const f4*)xs;
 #pragma unroll
           for (int m = 0; m < TM; ++m) xm[m][j] = v[m];
-        } else if (VEC && TM == 2 && lane_full && vp) {
+        } else if (VEC && TM == 2 && (MODE == 2 || (lane_full && vp))) {
           const f2 v = *(const f2*)xs;
 #pragma unroll
           for (int m = 0; m < TM; ++m) xm[m][j] = v[m];
@@ -497,20 +521,35 @@ __global__ void __launch_bounds__(64) modeB_bf16_kernel(const ModeJobs J, int64_
           for (int m = 0; m < TM; ++m) xm[m][j] = (vp && arow + m < na) ? xs[m] : 0.f;
         }
       }
-      bf8 ap[TM][NP], bp[TN][NP];
-#pragma unroll
-      for (int m = 0; m < TM; ++m) split_bf16<NP>(xm[m], ap[m]);
 #pragma unroll
       for (int u = 0; u < TN; ++u) {
         const int64_t off = (int64_t)(i0 + TN * l + u) * ldp + p0 + 8 * g;
 #pragma unroll
         for (int k = 0; k < NP; ++k) bp[u][k] = *(const bf8*)(PH + k * plane + off);
       }
+    };
+    auto cmp = [&](const f8 (&xm)[TM], const bf8 (&bp)[TN][NP]) {
+      bf8 ap[TM][NP];
+#pragma unroll
+      for (int m = 0; m < TM; ++m) split_bf16<NP>(xm[m], ap[m]);
 #pragma unroll
       for (int m = 0; m < TM; ++m)
 #pragma unroll
         for (int u = 0; u < TN; ++u) mfma_split<NP>(ap[m], bp[u], sc, acc[m][u], accs[m][u]);
+    };
+    f8 x0[TM], x1[TM];
+    bf8 q0[TN][NP], q1[TN][NP];
+    ldc(0, x0, q0);
+    int p0 = 0;
+    for (; p0 + 32 < n; p0 += 64) {
+      ldc(p0 + 32, x1, q1);
+      __builtin_amdgcn_sched_barrier(0);
+      cmp(x0, q0);
+      ldc(p0 + 64 < n ? p0 + 64 : p0, x0, q0);   // the last one re-reads a valid chunk
+      __builtin_amdgcn_sched_barrier(0);
+      cmp(x1, q1);
     }
+    if (p0 < n) cmp(x0, q0);
 #pragma unroll
     for (int m = 0; m < TM; ++m)
 #pragma unroll
@@ -544,27 +583,49 @@ int finish_tiles_lp(ModeJobs& J, bool mode1, int TM, int TN) {
 
 bool aligned_lp(const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
-constexpr int kTM1 = 4, kTN1 = 2;   // mode 1 wave tile (rows x columns of 16)
-constexpr int kTMB = 2, kTNB = 2;   // modes >= 2
+// bf16 wave tiles (rows x columns of 16): 4 x 4 on the interior path (one
+// wave per SIMD; swept at 3D FHN 256^3: BF16x3 113 steps/s against 97 for
+// 4 x 2 / 2 x 4 and 78 for 2 x 4 / 2 x 2), smaller ones on the masked paths,
+// whose larger register needs would spill at 4 x 4.
+constexpr int kTM1 = 4, kTN1 = 4;     // mode 1, interior
+constexpr int kTM1s = 4, kTN1s = 2;   // mode 1, masked
+constexpr int kTMB = 4, kTNB = 4;     // modes >= 2, interior
+constexpr int kTMBs = 2, kTNBs = 2;   // modes >= 2, masked
 
 }  // namespace
 
 namespace {
 
-template <bool VEC, typename T>
+template <int MODE, typename T>
 void go_mode1(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  constexpr int TM = MODE == 2 ? kTM1 : kTM1s, TN = MODE == 2 ? kTN1 : kTN1s;
   if (prec == SETD_PREC_BF16X3)
-    hipLaunchKernelGGL((mode1_bf16_kernel<3, kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
+    hipLaunchKernelGGL((mode1_bf16_kernel<3, TM, TN, MODE, T>), grid, dim3(64), 0, s, J, per);
   else
-    hipLaunchKernelGGL((mode1_bf16_kernel<2, kTM1, kTN1, VEC, T>), grid, dim3(64), 0, s, J, per);
+    hipLaunchKernelGGL((mode1_bf16_kernel<2, TM, TN, MODE, T>), grid, dim3(64), 0, s, J, per);
 }
 
-template <bool VEC, typename T>
+template <int MODE, typename T>
 void go_modeB(int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  constexpr int TM = MODE == 2 ? kTMB : kTMBs, TN = MODE == 2 ? kTNB : kTNBs;
   if (prec == SETD_PREC_BF16X3)
-    hipLaunchKernelGGL((modeB_bf16_kernel<3, kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
+    hipLaunchKernelGGL((modeB_bf16_kernel<3, TM, TN, MODE, T>), grid, dim3(64), 0, s, J, per);
   else
-    hipLaunchKernelGGL((modeB_bf16_kernel<2, kTMB, kTNB, VEC, T>), grid, dim3(64), 0, s, J, per);
+    hipLaunchKernelGGL((modeB_bf16_kernel<2, TM, TN, MODE, T>), grid, dim3(64), 0, s, J, per);
+}
+
+template <typename T>
+void go_mode1_m(int mode, int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  if (mode == 2) go_mode1<2, T>(prec, grid, s, J, per);
+  else if (mode == 1) go_mode1<1, T>(prec, grid, s, J, per);
+  else go_mode1<0, T>(prec, grid, s, J, per);
+}
+
+template <typename T>
+void go_modeB_m(int mode, int prec, dim3 grid, hipStream_t s, const ModeJobs& J, int64_t per) {
+  if (mode == 2) go_modeB<2, T>(prec, grid, s, J, per);
+  else if (mode == 1) go_modeB<1, T>(prec, grid, s, J, per);
+  else go_modeB<0, T>(prec, grid, s, J, per);
 }
 
 }  // namespace
@@ -660,46 +721,47 @@ int launch_modeB_f32c(ModeJobs& J, DType out, hipStream_t s) {
 
 int launch_mode1_lp(ModeJobs& J, int prec, DType out, hipStream_t s) {
   if (prec == SETD_PREC_F32) return launch_mode1_f32c(J, out, s);
-  finish_tiles_lp(J, true, kTM1, kTN1);
-  if (J.total_tiles == 0) return SETD_OK;
-  const int kc = prec == SETD_PREC_F32 ? 4 : 8;     // contiguous p per lane
-  bool vec = true;
+  bool vec = true, interior = true;
   for (int j = 0; j < J.njobs; ++j) {
     const ModeJob& jb = J.job[j];
-    vec = vec && (jb.n % kc == 0) && aligned_lp(jb.X[0], 4 * kc) && aligned_lp(jb.Y, 16) && aligned_lp(jb.base, 16);
+    vec = vec && (jb.n % 8 == 0) && aligned_lp(jb.X[0], 32) && aligned_lp(jb.Y, 16) && aligned_lp(jb.base, 16);
+    interior = interior && jb.n % 32 == 0 && jb.nb % (16 * kTN1) == 0;
   }
+  const int mode = vec ? (interior ? 2 : 1) : 0;
+  if (mode == 2) finish_tiles_lp(J, true, kTM1, kTN1);
+  else finish_tiles_lp(J, true, kTM1s, kTN1s);
+  if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
   if (prof_on()) job_work(J, 4, out == DType::F64 ? 8 : 4, 4, fl, by);
   ProfScope prof(s, kProfMode1LP, fl, by);
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
-  if (out == DType::F32)
-    vec ? go_mode1<true, float>(prec, grid, s, J, per) : go_mode1<false, float>(prec, grid, s, J, per);
-  else
-    vec ? go_mode1<true, double>(prec, grid, s, J, per) : go_mode1<false, double>(prec, grid, s, J, per);
+  if (out == DType::F32) go_mode1_m<float>(mode, prec, grid, s, J, per);
+  else go_mode1_m<double>(mode, prec, grid, s, J, per);
   SETD_LAUNCHED();
   return SETD_OK;
 }
 
 int launch_modeB_lp(ModeJobs& J, int prec, DType out, hipStream_t s) {
   if (prec == SETD_PREC_F32) return launch_modeB_f32c(J, out, s);
-  finish_tiles_lp(J, false, kTMB, kTNB);
-  if (J.total_tiles == 0) return SETD_OK;
-  bool vec = true;
+  bool vec = true, interior = true;
   for (int j = 0; j < J.njobs; ++j) {
     const ModeJob& jb = J.job[j];
     vec = vec && (jb.na % 4 == 0) && aligned_lp(jb.Y, 16) && aligned_lp(jb.base, 16);
     for (int t = 0; t < jb.nterms; ++t) vec = vec && aligned_lp(jb.X[t], 16);
+    interior = interior && jb.n % 32 == 0 && jb.na % (16 * kTMB) == 0;
   }
+  const int mode = vec ? (interior ? 2 : 1) : 0;
+  if (mode == 2) finish_tiles_lp(J, false, kTMB, kTNB);
+  else finish_tiles_lp(J, false, kTMBs, kTNBs);
+  if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
   if (prof_on()) job_work(J, 4, out == DType::F64 ? 8 : 4, 4, fl, by);
   ProfScope prof(s, kProfModeBLP, fl, by);
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
-  if (out == DType::F32)
-    vec ? go_modeB<true, float>(prec, grid, s, J, per) : go_modeB<false, float>(prec, grid, s, J, per);
-  else
-    vec ? go_modeB<true, double>(prec, grid, s, J, per) : go_modeB<false, double>(prec, grid, s, J, per);
+  if (out == DType::F32) go_modeB_m<float>(mode, prec, grid, s, J, per);
+  else go_modeB_m<double>(mode, prec, grid, s, J, per);
   SETD_LAUNCHED();
   return SETD_OK;
 }
