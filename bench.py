@@ -92,6 +92,47 @@ def copy_probe(mbytes, reps=5):
     log("copy probe: %d launches of a %d-byte read + %d-byte write" % (reps, n * 8, n * 8))
 
 
+def library_gemm(n=256, reps=20):
+    """The vendor library's FP64 GEMM (torch.matmul: hipBLASLt / rocBLAS) at the
+    mode-product shapes of an n^3 grid, as a reference point for the
+    library's own kernels (not part of the split-ETD3 path)."""
+    import torch
+    dev = "cuda"
+
+    def rate(f, flops, it=reps):
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(it):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / it
+        return {"tflops": round(flops / (ms * 1e-3) / 1e12, 2), "ms": round(ms, 4)}
+
+    g = torch.Generator(device=dev).manual_seed(0)
+    N = n ** 3
+    P = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+    X1 = torch.randn(n, N // n, dtype=torch.float64, device=dev, generator=g)
+    Y1 = torch.empty_like(X1)
+    XB = torch.randn(N // n, n, dtype=torch.float64, device=dev, generator=g)
+    YB = torch.empty_like(XB)
+    XM = torch.randn(n, n, n, dtype=torch.float64, device=dev, generator=g)
+    YM = torch.empty_like(XM)
+    PT = P.t().contiguous()
+    out = {"what": "torch.matmul FP64 at the mode-product shapes of a %d^3 grid (2 N n flops each)" % n,
+           "mode1_P_X": rate(lambda: torch.matmul(P, X1, out=Y1), 2.0 * N * n),
+           "last_mode_X_Pt": rate(lambda: torch.matmul(XB, PT, out=YB), 2.0 * N * n),
+           "middle_mode_batched": rate(lambda: torch.matmul(P, XM, out=YM), 2.0 * N * n)}
+    m = 8192
+    A = torch.randn(m, m, dtype=torch.float64, device=dev, generator=g)
+    B = torch.randn(m, m, dtype=torch.float64, device=dev, generator=g)
+    out["square_8192"] = rate(lambda: torch.matmul(A, B), 2.0 * m ** 3, it=5)
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(prob, nsteps):
     import numpy as np
     import oracle
@@ -253,6 +294,8 @@ def main():
                     help="forms to time besides the FP64 metric: f32, bf16x3, bf16x2 (compared against f64), "
                          "batch (64 uneven 2D Schnakenberg instances, 100 steps), methods (exprk3ds_cplx and "
                          "etd2rkds on the same workload) and adjoint (gradient of the 3D FHN 128^3, 200-step loss)")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="only time the vendor library's FP64 GEMM at the 256^3 mode-product shapes and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -263,6 +306,9 @@ def main():
 
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+        return
+    if args.library_gemm:
+        library_gemm()
         return
 
     import torch
