@@ -98,17 +98,21 @@ int setd_phi_matrices(const double* A, int64_t n, double tau, int ell, double* o
  *
  *   V, W   N-element tensors (device), FP64, must not overlap.
  *   d      1 <= d <= 8.
- *   dims   host array of d sizes, 1 <= n_mu <= 4096.
+ *   dims   host array of d sizes, 1 <= n_mu <= 4096, at most 2^36 elements
+ *          in all.
  *   M      host array of d device pointers; M[mu] is the n_mu x n_mu
  *          column-major FP64 matrix applied along mode mu+1.  NULL means the
  *          identity (that mode is skipped).
- *   prec   SETD_PREC_F64, SETD_PREC_F32 or SETD_PREC_BF16X3 (arithmetic of the
- *          mode products; V and W stay FP64).
+ *   prec   SETD_PREC_F64, SETD_PREC_F32, SETD_PREC_BF16X3 or SETD_PREC_BF16X2
+ *          (arithmetic of the mode products; V and W stay FP64).
  *   ws     device workspace of at least setd_tucker_workspace_bytes(d, dims,
  *          prec) bytes, or NULL to let the library use its own (grown on
  *          demand, kept until setd_release_workspace or process exit).
  *
- * beta = 0 ignores the old contents of W (NaN included).
+ * beta = 0 ignores the old contents of W (NaN included).  An argument error or
+ * a failed workspace allocation returns before W is touched.
+ * setd_tucker_workspace_bytes returns 0 for arguments setd_tucker_apply would
+ * reject.
  */
 int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims,
                       const double* const* M, double alpha, double beta, int prec,
@@ -241,7 +245,7 @@ int setd_etd_adjoint_step(setd_ctx* ctx, const double* u, double* ubar, int g_ki
  * unless setd_batch_set_tiles chose them or SETD_BATCH_TUNE=0).
  *
  * setd_batch_create
- *   nbatch  >= 1 instances.
+ *   nbatch  1 <= nbatch <= 65536 instances.
  *   d       2 or 3 (every instance).
  *   dims    host array of nbatch*d sizes: dims[b*d + mu] = n_{mu+1} of
  *           instance b, 2 <= n <= 1024 (grids may be non-square and differ

@@ -588,7 +588,7 @@ int setd_batch_create(setd_batch** out, int nbatch, int d, const int64_t* dims, 
   clear_error();
   SETD_CHECK_ARG(out != nullptr, "batch out-pointer is NULL");
   *out = nullptr;
-  SETD_CHECK_ARG(nbatch >= 1, "nbatch = %d < 1", nbatch);
+  SETD_CHECK_ARG(nbatch >= 1 && nbatch <= 65536, "nbatch = %d outside 1..65536", nbatch);
   SETD_CHECK_ARG(d == 2 || d == 3, "d = %d: the split integrator supports d = 2 and d = 3", d);
   SETD_CHECK_ARG(dims != nullptr && A != nullptr, "dims and A must be non-NULL");
   SETD_CHECK_ARG(ncomp == 1 || ncomp == 2, "ncomp = %d outside 1..2", ncomp);

@@ -41,6 +41,10 @@ void set_error(const char* fmt, ...) {
 }
 void clear_error() { g_err[0] = 0; }
 
+// Largest tensor setd_tucker_apply accepts: 2^36 elements (512 GiB in FP64,
+// more than one GPU holds); keeps every size product far from overflow.
+constexpr int64_t kMaxTuckerElems = int64_t(1) << 36;
+
 // ---- kernel timing ----
 namespace {
 struct ProfRec {
@@ -618,7 +622,7 @@ size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec) {
   int64_t N = 1;
   size_t pk = 0;
   for (int mu = 0; mu < d; ++mu) {
-    if (dims[mu] < 1 || dims[mu] > 4096) return 0;
+    if (dims[mu] < 1 || dims[mu] > 4096 || N > kMaxTuckerElems / dims[mu]) return 0;
     N *= dims[mu];
     pk += round_up(packed_bytes((int)dims[mu], prec), 256);
   }
@@ -637,6 +641,8 @@ int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, co
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) {
     SETD_CHECK_ARG(dims[mu] >= 1 && dims[mu] <= 4096, "dims[%d] = %lld outside 1..4096", mu, (long long)dims[mu]);
+    SETD_CHECK_ARG(N <= kMaxTuckerElems / dims[mu], "the tensor has more than %lld elements",
+                   (long long)kMaxTuckerElems);
     N *= dims[mu];
   }
   SETD_CHECK_ARG(!overlap(V, N * 8, W, N * 8), "V and W overlap");
@@ -652,20 +658,27 @@ int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, co
   int modes[8], nm = 0;
   for (int mu = 0; mu < d; ++mu)
     if (M[mu] != nullptr) modes[nm++] = mu;
+  // the workspace first, so that a failed allocation leaves W untouched
+  void* wsp = ws;
+  bool own = false;
+  if (nm > 0 && wsp == nullptr) {
+    SETD_HIP(hipMallocAsync(&wsp, need, s));
+    own = true;
+  }
   // beta handling: base = W when beta == 1, none when beta == 0, else scale W first
   const double* base = nullptr;
   if (beta != 0.0) {
-    if (beta != 1.0) SETD_TRY(launch_scale(W, N, beta, s));
+    if (beta != 1.0) {
+      const int r = launch_scale(W, N, beta, s);
+      if (r != SETD_OK) {
+        if (own) (void)hipFreeAsync(wsp, s);
+        return r;
+      }
+    }
     base = W;
   }
   if (nm == 0) {
     return launch_axpby(V, W, N, alpha, beta == 0.0 ? 0.0 : 1.0, s);
-  }
-  void* wsp = ws;
-  bool own = false;
-  if (wsp == nullptr) {
-    SETD_HIP(hipMallocAsync(&wsp, need, s));
-    own = true;
   }
   const bool lp = prec != SETD_PREC_F64;
   const int64_t fb = round_up(N * 8, 256);

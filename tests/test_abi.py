@@ -46,6 +46,11 @@ def test_workspace_size_is_host_only():
     assert lib.setd_tucker_workspace_bytes(0, dims, _lib.PREC_F64) == 0
     bad = (ctypes.c_int64 * 3)(256, 0, 256)
     assert lib.setd_tucker_workspace_bytes(3, bad, _lib.PREC_F64) == 0
+    # more than 2^36 elements: rejected before any size product can overflow
+    huge = (ctypes.c_int64 * 8)(*([4096] * 8))
+    assert lib.setd_tucker_workspace_bytes(8, huge, _lib.PREC_F64) == 0
+    edge = (ctypes.c_int64 * 3)(4096, 4096, 4096)          # exactly 2^36
+    assert lib.setd_tucker_workspace_bytes(3, edge, _lib.PREC_F64) > 2 ** 36 * 8
 
 
 def test_validation_errors_before_any_launch():
@@ -65,12 +70,18 @@ def test_validation_errors_before_any_launch():
     dd = (ctypes.c_int64 * 2)(4, 4)
     M = (ctypes.c_void_p * 2)()
     assert lib.setd_tucker_apply(None, None, 2, dd, M, 1.0, 0.0, 0, None, 0, None) == _lib.SETD_EINVAL
+    huge = (ctypes.c_int64 * 8)(*([4096] * 8))
+    M8 = (ctypes.c_void_p * 8)()
+    assert lib.setd_tucker_apply(ctypes.c_void_p(4096), ctypes.c_void_p(8192), 8, huge, M8, 1.0, 0.0, 0, None, 0,
+                                 None) == _lib.SETD_EINVAL
+    assert b"elements" in lib.setd_last_error()
     out = (ctypes.c_double * 4)()
     assert lib.setd_field_norms(None, None, 10, out, None) == _lib.SETD_EINVAL
     # batch: bad sizes, NULL matrices, reduced precision (FP64 only)
     bd = (ctypes.c_int64 * 4)(16, 16, 1, 16)
     BA = (ctypes.c_void_p * 8)(*([1] * 8))
     assert lib.setd_batch_create(ctypes.byref(h), 0, 2, bd, 2, BA, 0.01, 0, None) == _lib.SETD_EINVAL
+    assert lib.setd_batch_create(ctypes.byref(h), 65537, 2, bd, 2, BA, 0.01, 0, None) == _lib.SETD_EINVAL
     assert lib.setd_batch_create(ctypes.byref(h), 2, 2, bd, 2, BA, 0.01, 0, None) == _lib.SETD_EINVAL   # n = 1
     bd[2] = 16
     assert lib.setd_batch_create(ctypes.byref(h), 2, 2, bd, 2, (ctypes.c_void_p * 8)(), 0.01, 0,
