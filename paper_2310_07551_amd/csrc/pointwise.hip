@@ -212,18 +212,65 @@ __device__ __forceinline__ void stage_d_point(const double* __restrict__ Us, con
   for (int c = 0; c < ncomp; ++c) D[(int64_t)c * cs + idx] = (TD)(g[c] - G[(int64_t)c * cs + idx]);
 }
 
-// One thread per grid point.  Writes G_c = g_c(u) and F_c = (K_c u_c) + G_c
-// for every component (F in FP64, or FP32 for the reduced-precision Tuckers).
-// The grid is (ceil(n1 / blockDim.x), n2, n3): the grid indices come from
-// the block coordinates, with no integer division per point.
-template <typename TF>
+// Writes G_c = g_c(u) and F_c = (K_c u_c) + G_c for every component (F in
+// FP64, or FP32 for the reduced-precision Tuckers).  Each thread owns one i1
+// and walks RB consecutive i2 rows of one i3 plane, carrying the previous,
+// current and next row values of every component in registers, so each
+// i2 neighbour is loaded once; the i1 and i3 coefficients are loaded once
+// per thread.  The grid is (ceil(n1 / blockDim.x), ceil(n2 / RB), n3): no
+// integer division per point.  The sums are formed in the order of
+// gf_point_at (direction by direction).
+template <typename TF, int RB>
 __global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64_t N, int d, int n1, int n2,
                                   int n3, StencilSet S, GParams gp, double* __restrict__ G, TF* __restrict__ F) {
   const int i1 = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i1 >= n1) return;
-  const int i2 = (int)blockIdx.y, i3 = (int)blockIdx.z;
-  const int64_t idx = ((int64_t)i3 * n2 + i2) * n1 + i1;
-  gf_point_at<TF>(u, N, idx, i1, i2, i3, ncomp, d, n1, n2, n3, S, gp, G, F);
+  const int r0 = (int)blockIdx.y * RB, i3 = (int)blockIdx.z;
+  const int64_t s2 = n1, s3 = (int64_t)n1 * n2;
+  const int64_t base = (int64_t)i3 * s3 + i1;
+  double d1[2], l1[2], u1[2], d3[2], l3[2], u3[2], prv[2], cur[2];
+  for (int c = 0; c < ncomp; ++c) {
+    const int o1 = c * 3, o3 = c * 3 + 2;
+    d1[c] = S.di[o1][i1];
+    l1[c] = i1 > 0 ? S.lo[o1][i1] : 0.0;
+    u1[c] = i1 + 1 < n1 ? S.up[o1][i1] : 0.0;
+    d3[c] = d == 3 ? S.di[o3][i3] : 0.0;
+    l3[c] = (d == 3 && i3 > 0) ? S.lo[o3][i3] : 0.0;
+    u3[c] = (d == 3 && i3 + 1 < n3) ? S.up[o3][i3] : 0.0;
+    prv[c] = r0 > 0 ? u[c * N + base + (int64_t)(r0 - 1) * s2] : 0.0;
+    cur[c] = u[c * N + base + (int64_t)r0 * s2];
+  }
+  for (int r = 0; r < RB; ++r) {
+    const int i2 = r0 + r;
+    if (i2 >= n2) break;
+    const int64_t idx = base + (int64_t)i2 * s2;
+    double nxt[2] = {0.0, 0.0}, g[2];
+    for (int c = 0; c < ncomp; ++c) nxt[c] = i2 + 1 < n2 ? u[c * N + idx + s2] : 0.0;
+    reaction(gp, cur[0], ncomp > 1 ? cur[1] : 0.0, g[0], g[1]);
+    for (int c = 0; c < ncomp; ++c) {
+      const double* __restrict__ uu = u + (int64_t)c * N;
+      const int o2 = c * 3 + 1;
+      double t = d1[c] * cur[c];
+      if (i1 > 0) t += l1[c] * uu[idx - 1];
+      if (i1 + 1 < n1) t += u1[c] * uu[idx + 1];
+      double k = 0.0;
+      k += t;
+      t = S.di[o2][i2] * cur[c];
+      if (i2 > 0) t += S.lo[o2][i2] * prv[c];
+      if (i2 + 1 < n2) t += S.up[o2][i2] * nxt[c];
+      k += t;
+      if (d == 3) {
+        t = d3[c] * cur[c];
+        if (i3 > 0) t += l3[c] * uu[idx - s3];
+        if (i3 + 1 < n3) t += u3[c] * uu[idx + s3];
+        k += t;
+      }
+      G[(int64_t)c * N + idx] = g[c];
+      F[(int64_t)c * N + idx] = (TF)(k + g[c]);
+      prv[c] = cur[c];
+      cur[c] = nxt[c];
+    }
+  }
 }
 
 // G_c = g_c(u) only (the dense-K path adds the mode products afterwards).
@@ -286,16 +333,17 @@ int launch_batch_pointwise(int kind, const BatchInstDev* inst, const int64_t* bl
 int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* dims, const StencilSet& S,
                       const GParams& gp, double* G, void* F, DType ftype, hipStream_t s) {
   const int n3 = d == 3 ? dims[2] : 1;
+  constexpr int RB = 8;   // i2 rows per thread
   const int bx = (int)std::min<int64_t>(256, round_up(dims[0], 64));
-  const dim3 grid((unsigned)ceil_div(dims[0], bx), (unsigned)dims[1], (unsigned)n3);
+  const dim3 grid((unsigned)ceil_div(dims[0], bx), (unsigned)ceil_div(dims[1], RB), (unsigned)n3);
   // reads u once, writes G (FP64) and F
   ProfScope prof(s, kProfPointwise, 0.0, (double)N * ncomp * (8 + 8 + (ftype == DType::F64 ? 8 : 4)));
   if (ftype == DType::F64)
-    hipLaunchKernelGGL(gf_stencil_kernel<double>, grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S,
-                       gp, G, (double*)F);
+    hipLaunchKernelGGL((gf_stencil_kernel<double, RB>), grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3,
+                       S, gp, G, (double*)F);
   else
-    hipLaunchKernelGGL(gf_stencil_kernel<float>, grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S, gp,
-                       G, (float*)F);
+    hipLaunchKernelGGL((gf_stencil_kernel<float, RB>), grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S,
+                       gp, G, (float*)F);
   SETD_LAUNCHED();
   return SETD_OK;
 }
