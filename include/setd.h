@@ -231,6 +231,31 @@ int setd_etd_adjoint_step(setd_ctx* ctx, const double* u, double* ubar, int g_ki
                           void* stream);
 
 /*
+ * One split-ETD3 step that also keeps the step's stage quantities, for a
+ * later setd_etd_adjoint_step_recorded (a checkpointed backward pass steps
+ * forward from a checkpoint anyway; recording there spares the adjoint step
+ * its own forward recomputation of the stages).
+ *
+ *   u     as for setd_etd_step (one step, in place).
+ *   rec   6 * ncomp * N doubles (device), written: G = g(U), F = K U + G,
+ *         U2, D2 = g(U2) - G, U3, D3 = g(U3) - G (eq. exprk3 with the split
+ *         phi actions), each ncomp * N, component-major.  Must not overlap u.
+ * FP64 contexts only.  Plain launches (no graph replay).
+ */
+int setd_etd_step_record(setd_ctx* ctx, double* u, double tau, int g_kind, const double* params,
+                         int nparams, double* rec, void* stream);
+
+/*
+ * setd_etd_adjoint_step with the stage quantities of the step taken from
+ * `rec`, as setd_etd_step_record wrote them for the same u, tau and
+ * parameters (read only; must not overlap ubar).  Same results as
+ * setd_etd_adjoint_step, without its forward recomputation.
+ */
+int setd_etd_adjoint_step_recorded(setd_ctx* ctx, const double* u, const double* rec, double* ubar,
+                                   int g_kind, const double* params, int nparams, int sigma_mask,
+                                   double* grad, void* stream);
+
+/*
  * Batched integration: nbatch independent instances of one kind of problem
  * (same d, ncomp and tau; each with its own grid, matrices A_mu^(c) and
  * reaction parameters) advanced together by split-ETD3 steps (the same step

@@ -204,11 +204,31 @@ class Context:
         self.tau = t
         return u
 
+    def step_record(self, u, rec, g_kind: int, params: Sequence[float], tau: Optional[float] = None,
+                    stream=None):
+        """One split-ETD3 step of u in place that also writes the step's stage
+        quantities (G, F, U2, D2, U3, D3; 6*ncomp*N FP64) into rec, for
+        adjoint_step(..., rec=rec) (setd_etd_step_record)."""
+        _check_dev(u, "u")
+        _check_dev(rec, "rec")
+        if u.numel() != self.ncomp * self.N:
+            raise ValueError("u must hold ncomp*N values")
+        if rec.numel() < 6 * self.ncomp * self.N:
+            raise ValueError("rec needs 6*ncomp*N values")
+        p = (ctypes.c_double * max(1, len(params)))(*[float(x) for x in params])
+        t = self.tau if tau is None else float(tau)
+        _lib.check(_lib.load().setd_etd_step_record(self._h, u.data_ptr(), t, int(g_kind), p, len(params),
+                                                    rec.data_ptr(), _stream(stream)))
+        self.tau = t
+        return u
+
     def adjoint_step(self, u, ubar, g_kind: int, params: Sequence[float], grad, sigma_mask: int = 0,
-                     stream=None):
+                     rec=None, stream=None):
         """One step backwards: ubar <- (dU'/dU)^T ubar at state u; grad (FP64
         device, len(params) + ncomp) accumulates the parameter and diffusion-size
-        gradients (setd_etd_adjoint_step)."""
+        gradients (setd_etd_adjoint_step).  With rec (written by step_record
+        for this u) the stage quantities are not recomputed
+        (setd_etd_adjoint_step_recorded)."""
         _check_dev(u, "u")
         _check_dev(ubar, "ubar")
         _check_dev(grad, "grad")
@@ -217,8 +237,17 @@ class Context:
         if grad.numel() < len(params) + self.ncomp:
             raise ValueError("grad needs len(params) + ncomp entries")
         p = (ctypes.c_double * max(1, len(params)))(*[float(x) for x in params])
-        _lib.check(_lib.load().setd_etd_adjoint_step(self._h, u.data_ptr(), ubar.data_ptr(), int(g_kind), p,
-                                                     len(params), int(sigma_mask), grad.data_ptr(), _stream(stream)))
+        lib = _lib.load()
+        if rec is None:
+            _lib.check(lib.setd_etd_adjoint_step(self._h, u.data_ptr(), ubar.data_ptr(), int(g_kind), p, len(params),
+                                                 int(sigma_mask), grad.data_ptr(), _stream(stream)))
+        else:
+            _check_dev(rec, "rec")
+            if rec.numel() < 6 * self.ncomp * self.N:
+                raise ValueError("rec needs 6*ncomp*N values")
+            _lib.check(lib.setd_etd_adjoint_step_recorded(self._h, u.data_ptr(), rec.data_ptr(), ubar.data_ptr(),
+                                                          int(g_kind), p, len(params), int(sigma_mask),
+                                                          grad.data_ptr(), _stream(stream)))
         return ubar
 
     def step2(self, u, nsteps: int, g_kind: int, params: Sequence[float], tau: Optional[float] = None,

@@ -44,6 +44,9 @@ SIGNATURES = {
     "setd_ctx_destroy": (_c_int, [_vp]),
     "setd_split_phi_apply": (_c_int, [_vp, _c_int, _c_int, _c_int, _vp, _vp, _c_double, _c_double, _vp]),
     "setd_etd_step": (_c_int, [_vp, _vp, _c_int, _c_double, _c_int, ctypes.POINTER(_c_double), _c_int, _vp]),
+    "setd_etd_step_record": (_c_int, [_vp, _vp, _c_double, _c_int, ctypes.POINTER(_c_double), _c_int, _vp, _vp]),
+    "setd_etd_adjoint_step_recorded": (_c_int, [_vp, _vp, _vp, _vp, _c_int, ctypes.POINTER(_c_double), _c_int,
+                                                _c_int, _vp, _vp]),
     "setd_etd2_step": (_c_int, [_vp, _vp, _c_int, _c_double, _c_int, ctypes.POINTER(_c_double), _c_int, _vp]),
     "setd_etd_cplx_step": (_c_int, [_vp, _vp, _c_int, _c_double, _c_int, ctypes.POINTER(_c_double), _c_int, _vp]),
     "setd_field_norms": (_c_int, [_vp, _vp, _c_i64, ctypes.POINTER(_c_double), _vp]),

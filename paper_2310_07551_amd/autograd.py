@@ -25,7 +25,7 @@ class _Integrate(_torch().autograd.Function):
     @staticmethod
     def forward(fctx, u0, params, diff, spec):
         torch = _torch()
-        dims, D, g_kind, tau, nsteps, checkpoint, diff_components = spec
+        dims, D, g_kind, tau, nsteps, checkpoint, diff_components = spec[:7]
         ncomp = len(D)
         dvals = [float(x) for x in diff.detach().cpu()]
         pvals = [float(x) for x in params.detach().cpu()]
@@ -48,7 +48,7 @@ class _Integrate(_torch().autograd.Function):
     def backward(fctx, grad_u):
         torch = _torch()
         ctx, checkpoints, pvals, dvals, spec = fctx.setd
-        dims, D, g_kind, tau, nsteps, checkpoint, diff_components = spec
+        dims, D, g_kind, tau, nsteps, checkpoint, diff_components = spec[:7]
         ncomp = len(D)
         ubar = grad_u.detach().to(torch.float64).contiguous().clone()
         grad = torch.zeros(len(pvals) + ncomp, dtype=torch.float64, device=ubar.device)
@@ -59,16 +59,24 @@ class _Integrate(_torch().autograd.Function):
         if fctx.needs_input_grad[2]:
             for c in (range(ncomp) if diff_components is None else diff_components):
                 mask |= 1 << int(c)
+        record = spec_record(spec)
+        recs = None
         for seg in range(len(checkpoints) - 1, -1, -1):
             k = min(checkpoint, nsteps - seg * checkpoint)
             states = torch.empty((k, ubar.numel()), dtype=torch.float64, device=ubar.device)
+            if record and recs is None:
+                # stage quantities of every step of a segment (6 ncomp N each)
+                recs = torch.empty((checkpoint, 6 * ubar.numel()), dtype=torch.float64, device=ubar.device)
             work.copy_(checkpoints[seg])
             for j in range(k):
                 states[j].copy_(work)
-                if j + 1 < k:
+                if record:
+                    ctx.step_record(work, recs[j], g_kind, pvals)
+                elif j + 1 < k:
                     ctx.step(work, 1, g_kind, pvals)
             for j in range(k - 1, -1, -1):
-                ctx.adjoint_step(states[j], ubar, g_kind, pvals, grad, sigma_mask=mask)
+                ctx.adjoint_step(states[j], ubar, g_kind, pvals, grad, sigma_mask=mask,
+                                 rec=recs[j] if record else None)
         g = grad.cpu()
         gp = g[:len(pvals)].clone()
         gd = torch.tensor([g[len(pvals) + c].item() / dvals[c] if (mask >> c) & 1 else 0.0 for c in range(ncomp)],
@@ -78,16 +86,24 @@ class _Integrate(_torch().autograd.Function):
         return ubar, gp.to(fctx.devices[0]), gd.to(fctx.devices[1]), None
 
 
+def spec_record(spec) -> bool:
+    return bool(spec[7]) if len(spec) > 7 else True
+
+
 def integrate(u0, params, diff, *, dims: Sequence[int], D, g_kind: int, tau: float, nsteps: int,
-              checkpoint: int = 20, diff_components=None):
+              checkpoint: int = 20, diff_components=None, record: bool = True):
     """u(T) after nsteps split-ETD3 steps from u0 (flat FP64 device tensor,
     component-major), differentiable in u0, params (1-D tensor of reaction
     parameters) and diff (1-D tensor, one diffusion coefficient per
     component; A_mu^(c) = diff[c] * D[c][mu], D column-major FP64 device
     matrices).  diff_components: the components whose diffusion gradient is
-    wanted (default all; the others get 0)."""
+    wanted (default all; the others get 0).  The backward pass steps forward
+    from each checkpoint again; with record (default) those steps keep their
+    stage quantities (6 ncomp N doubles per step of a segment) so that the
+    adjoint steps need not recompute them."""
     if checkpoint < 1:
         raise ValueError("checkpoint must be >= 1")
     comps = None if diff_components is None else tuple(int(c) for c in diff_components)
-    spec = (tuple(int(x) for x in dims), D, int(g_kind), float(tau), int(nsteps), int(checkpoint), comps)
+    spec = (tuple(int(x) for x in dims), D, int(g_kind), float(tau), int(nsteps), int(checkpoint), comps,
+            bool(record))
     return _Integrate.apply(u0, params, diff, spec)

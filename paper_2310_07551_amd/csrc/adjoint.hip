@@ -273,8 +273,8 @@ TuckerOut mk_out(double* Y, const double* base, const void* X, void* const (*P)[
   return o;
 }
 
-int adjoint_step(setd_ctx* c, const double* u_in, double* ubar, const GParams& gp, int nparams, int sigma_mask,
-                 double* grad, hipStream_t s) {
+int adjoint_step(setd_ctx* c, const double* u_in, const double* rec, double* ubar, const GParams& gp, int nparams,
+                 int sigma_mask, double* grad, hipStream_t s) {
   const int d = c->d, nc = c->ncomp, T = c->nterms;
   const int64_t N = c->N;
   const double tau = c->tau;
@@ -284,28 +284,39 @@ int adjoint_step(setd_ctx* c, const double* u_in, double* ubar, const GParams& g
   const double* eta1 = c->sp[1].eta;
   const double* eta2 = c->sp[2].eta;
   auto at = [&](double* p, int cc) { return p + (int64_t)cc * N; };
-  // ---- forward recomputation: G, F, U2, D2, U3, D3 ----
-  SETD_TRY(compute_gf(c, u, gp, s));
-  {
-    TuckerOut outs[4];
-    int no = 0;
-    for (int cc = 0; cc < nc; ++cc) {
-      outs[no++] = mk_out(at(c->U2, cc), at(u, cc), at(c->F, cc), c->bank[cc][e21], tau / 3.0, eta1, T,
-                          &c->Y1[cc][0], &c->Y2[cc][0]);
-      outs[no++] = mk_out(at(c->U3, cc), at(u, cc), at(c->F, cc), c->bank[cc][e31], 2.0 * tau / 3.0, eta1, T,
-                          &c->Y1[cc][T], &c->Y2[cc][T]);
+  // ---- the step's stage quantities G, F, U2, D2, U3, D3: recorded by
+  // setd_etd_step_record, or recomputed here ----
+  const int64_t NC = (int64_t)nc * N;
+  double* rw = const_cast<double*>(rec);   // read only below
+  double* const sG = rec ? rw : c->G;
+  double* const sF = rec ? rw + NC : c->F;
+  double* const sU2 = rec ? rw + 2 * NC : c->U2;
+  double* const sD2 = rec ? rw + 3 * NC : c->aD2;
+  double* const sU3 = rec ? rw + 4 * NC : c->U3;
+  double* const sD3 = rec ? rw + 5 * NC : c->aD3;
+  if (!rec) {
+    SETD_TRY(compute_gf(c, u, gp, s));
+    {
+      TuckerOut outs[4];
+      int no = 0;
+      for (int cc = 0; cc < nc; ++cc) {
+        outs[no++] = mk_out(at(sU2, cc), at(u, cc), at(sF, cc), c->bank[cc][e21], tau / 3.0, eta1, T,
+                            &c->Y1[cc][0], &c->Y2[cc][0]);
+        outs[no++] = mk_out(at(sU3, cc), at(u, cc), at(sF, cc), c->bank[cc][e31], 2.0 * tau / 3.0, eta1, T,
+                            &c->Y1[cc][T], &c->Y2[cc][T]);
+      }
+      SETD_TRY(run_tucker_group(d, c->dims, outs, no, SETD_PREC_F64, s));
     }
-    SETD_TRY(run_tucker_group(d, c->dims, outs, no, SETD_PREC_F64, s));
+    SETD_TRY(launch_stage_d(sU2, sG, nc, N, gp, sD2, DType::F64, s));
+    {
+      TuckerOut outs[2];
+      for (int cc = 0; cc < nc; ++cc)
+        outs[cc] = mk_out(at(sU3, cc), at(sU3, cc), at(sD2, cc), c->bank[cc][e32], 4.0 * tau / 3.0, eta2, T,
+                          &c->Y1[cc][0], &c->Y2[cc][0]);
+      SETD_TRY(run_tucker_group(d, c->dims, outs, nc, SETD_PREC_F64, s));
+    }
+    SETD_TRY(launch_stage_d(sU3, sG, nc, N, gp, sD3, DType::F64, s));
   }
-  SETD_TRY(launch_stage_d(c->U2, c->G, nc, N, gp, c->aD2, DType::F64, s));
-  {
-    TuckerOut outs[2];
-    for (int cc = 0; cc < nc; ++cc)
-      outs[cc] = mk_out(at(c->U3, cc), at(c->U3, cc), at(c->aD2, cc), c->bank[cc][e32], 4.0 * tau / 3.0, eta2, T,
-                        &c->Y1[cc][0], &c->Y2[cc][0]);
-    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, SETD_PREC_F64, s));
-  }
-  SETD_TRY(launch_stage_d(c->U3, c->G, nc, N, gp, c->aD3, DType::F64, s));
 
   // ---- diffusion-size derivatives of the split actions applied to their inputs ----
   // Ef = tau dS1(f) F + 3tau/2 dS2(f) D3, E3 = 2tau/3 dS1(3) F + 4tau/3 dS2(3) D2,
@@ -326,10 +337,10 @@ int adjoint_step(setd_ctx* c, const double* u_in, double* ubar, const GParams& g
             double mult;
             const double* eta;
           } spec[3] = {
-              {c->Ef, a == 0 ? c->F : c->aD3, a == 0 ? ef1 : ef2, a == 0 ? tau : 1.5 * tau, a == 0 ? eta1 : eta2},
-              {c->E3, a == 0 ? c->F : c->aD2, a == 0 ? e31 : e32, a == 0 ? 2.0 * tau / 3.0 : 4.0 * tau / 3.0,
+              {c->Ef, a == 0 ? sF : sD3, a == 0 ? ef1 : ef2, a == 0 ? tau : 1.5 * tau, a == 0 ? eta1 : eta2},
+              {c->E3, a == 0 ? sF : sD2, a == 0 ? e31 : e32, a == 0 ? 2.0 * tau / 3.0 : 4.0 * tau / 3.0,
                a == 0 ? eta1 : eta2},
-              {c->E2, c->F, e21, tau / 3.0, eta1}};
+              {c->E2, sF, e21, tau / 3.0, eta1}};
           const int nout = a == 0 ? 3 : 2;   // E2 has a phi_1 action only
           for (int k = 0; k < nout; ++k) {
             double* E = at(spec[k].E, cc);
@@ -366,7 +377,7 @@ int adjoint_step(setd_ctx* c, const double* u_in, double* ubar, const GParams& g
   }
   const dim3 rg(kRedBlocks), rb(kRedThreads);
   // D3 = g(U3) - G
-  hipLaunchKernelGGL(adj_stage_kernel, rg, rb, 0, s, c->U3, c->Dbar, nc, N, gp, c->U3bar, c->Gbar, true, c->part,
+  hipLaunchKernelGGL(adj_stage_kernel, rg, rb, 0, s, sU3, c->Dbar, nc, N, gp, c->U3bar, c->Gbar, true, c->part,
                      kRowP1);
   SETD_LAUNCHED();
   // U3 = U + 2tau/3 S1(3) F + 4tau/3 S2(3) D2
@@ -382,7 +393,7 @@ int adjoint_step(setd_ctx* c, const double* u_in, double* ubar, const GParams& g
     SETD_TRY(run_tucker_group(d, c->dims, outs, no, SETD_PREC_F64, s));
   }
   // D2 = g(U2) - G
-  hipLaunchKernelGGL(adj_stage_kernel, rg, rb, 0, s, c->U2, c->Dbar, nc, N, gp, c->U2bar, c->Gbar, false, c->part,
+  hipLaunchKernelGGL(adj_stage_kernel, rg, rb, 0, s, sU2, c->Dbar, nc, N, gp, c->U2bar, c->Gbar, false, c->part,
                      kRowP2);
   SETD_LAUNCHED();
   // U2 = U + tau/3 S1(2) F
@@ -419,7 +430,7 @@ int adjoint_step(setd_ctx* c, const double* u_in, double* ubar, const GParams& g
     ktf = c->KtF;
   }
   const int n3 = d == 3 ? c->dims[2] : 1;
-  hipLaunchKernelGGL(adj_final_kernel, rg, rb, 0, s, u, ubar, c->U3bar, c->U2bar, c->Fbar, c->Gbar, c->F, c->G, ktf,
+  hipLaunchKernelGGL(adj_final_kernel, rg, rb, 0, s, u, ubar, c->U3bar, c->U2bar, c->Fbar, c->Gbar, sF, sG, ktf,
                      nc, N, d, c->dims[0], c->dims[1], n3, c->st, gp, c->part);
   SETD_LAUNCHED();
   hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(64), 0, s, c->part, nparams, nc, sigma_mask, dots, grad);
@@ -450,5 +461,29 @@ extern "C" int setd_etd_adjoint_step(setd_ctx* c, const double* u, double* ubar,
   hipStream_t s = (hipStream_t)stream;
   if (c->adj_bank_mem.p == nullptr || c->adj_tau != c->tau) SETD_TRY(build_adjoint_bank(c, s));
   if (c->adj_mem.p == nullptr) SETD_TRY(alloc_adjoint_buffers(c));
-  return adjoint_step(c, u, ubar, gp, nparams, sigma_mask, grad, s);
+  return adjoint_step(c, u, nullptr, ubar, gp, nparams, sigma_mask, grad, s);
+}
+
+extern "C" int setd_etd_adjoint_step_recorded(setd_ctx* c, const double* u, const double* rec, double* ubar,
+                                              int g_kind, const double* params, int nparams, int sigma_mask,
+                                              double* grad, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(c != nullptr, "ctx is NULL");
+  SETD_CHECK_ARG(u != nullptr && rec != nullptr && ubar != nullptr, "u, rec and ubar must be non-NULL");
+  SETD_CHECK_ARG(sigma_mask >= 0 && sigma_mask < (1 << c->ncomp), "sigma_mask %d has bits beyond the components",
+                 sigma_mask);
+  SETD_CHECK_ARG(grad != nullptr || (nparams == 0 && sigma_mask == 0), "grad is NULL");
+  const int64_t NC = c->ncomp * c->N;
+  SETD_CHECK_ARG(!overlap(u, NC * 8, ubar, NC * 8), "u and ubar overlap");
+  SETD_CHECK_ARG(!overlap(rec, 6 * NC * 8, ubar, NC * 8), "rec and ubar overlap");
+  if (c->prec != SETD_PREC_F64) {
+    set_error("the adjoint step runs in FP64 only");
+    return SETD_EUNSUPPORTED;
+  }
+  GParams gp;
+  SETD_TRY(make_gparams(g_kind, params, nparams, c->ncomp, gp));
+  hipStream_t s = (hipStream_t)stream;
+  if (c->adj_bank_mem.p == nullptr || c->adj_tau != c->tau) SETD_TRY(build_adjoint_bank(c, s));
+  if (c->adj_mem.p == nullptr) SETD_TRY(alloc_adjoint_buffers(c));
+  return adjoint_step(c, u, rec, ubar, gp, nparams, sigma_mask, grad, s);
 }

@@ -80,8 +80,22 @@ struct TuckerOut {
 int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s);
 // Packs a matrix for the mode kernels of the given arithmetic and direction.
 int pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s);
-// G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type.
-int compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s);
+// G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type,
+// into c->G and c->F, or into G and F when given (FP64 contexts).
+int compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, double* G = nullptr, void* F = nullptr);
+// The stage quantities of one exprk3ds_real step, each ncomp * N: G = g(U),
+// F = K U + G, U2, D2 = g(U2) - G, U3, D3 = g(U3) - G.  F, D2 and D3 are in
+// the Tucker arithmetic's storage type.
+struct StageBufs {
+  double* G;
+  void* F;
+  double* U2;
+  void* D2;
+  double* U3;
+  void* D3;
+};
+// One step that keeps its stage quantities in `b` (setd_etd_step_record).
+int step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, const StageBufs& b);
 // Launches FP64 mode-product jobs of one regime in groups of kMaxJobs.
 int launch_f64_jobs(std::vector<ModeJob>& jobs, bool mode1, hipStream_t s);
 // exprk3ds_cplx (cplx.hip): complex phi bank for step size tau (synchronises

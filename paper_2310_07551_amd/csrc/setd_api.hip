@@ -321,24 +321,26 @@ int build_bank(setd_ctx* c, hipStream_t s) {
 // G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type.
 }  // namespace
 
-int setd::compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+int setd::compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, double* G, void* F) {
   const int d = c->d, nc = c->ncomp;
   const int64_t N = c->N;
   const bool lp = c->prec != SETD_PREC_F64;
   const DType tdt = lp ? DType::F32 : DType::F64;
   const size_t es = lp ? 4 : 8;
-  auto Fc_ = [&](int cc) { return (void*)((char*)c->F + cc * N * es); };
+  if (G == nullptr) G = c->G;
+  if (F == nullptr) F = c->F;
+  auto Fc_ = [&](int cc) { return (void*)((char*)F + cc * N * es); };
   if (c->tridiag) {
-    SETD_TRY(launch_gf_stencil(u, nc, N, d, c->dims, c->st, gp, c->G, c->F, tdt, s));
+    SETD_TRY(launch_gf_stencil(u, nc, N, d, c->dims, c->st, gp, G, F, tdt, s));
   } else {
-    SETD_TRY(launch_g(u, nc, N, gp, c->G, s));
+    SETD_TRY(launch_g(u, nc, N, gp, G, s));
     for (int cc = 0; cc < nc; ++cc) {
       // FP64 K action into F (or, reduced precision, into W then rounded)
-      double* Fc = lp ? c->W + cc * N : c->F + cc * N;
+      double* Fc = lp ? c->W + cc * N : (double*)F + cc * N;
       const double* uc = u + cc * N;
       ModeJobs J;
       J.njobs = 1;
-      J.job[0] = mk_job(uc, c->Apk[cc][0], 1.0, Fc, c->G + cc * N, 1, c->dims[0], N / c->dims[0]);
+      J.job[0] = mk_job(uc, c->Apk[cc][0], 1.0, Fc, G + cc * N, 1, c->dims[0], N / c->dims[0]);
       SETD_TRY(launch_mode1_f64(J, s));
       int64_t na = c->dims[0];
       for (int mu = 1; mu < d; ++mu) {
@@ -355,8 +357,11 @@ int setd::compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
 
 namespace {
 
-// One exprk3ds_real step (the time loop of Algorithms 1 and 2).
-int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+}  // namespace
+
+// One exprk3ds_real step (the time loop of Algorithms 1 and 2), its stage
+// quantities in b.
+int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, const StageBufs& b) {
   const int d = c->d, nc = c->ncomp, T = c->nterms;
   const int64_t N = c->N;
   const double tau = c->tau;
@@ -364,10 +369,11 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
   const bool lp = prec != SETD_PREC_F64;
   const DType tdt = lp ? DType::F32 : DType::F64;   // type of F, D and the intermediates
   const size_t es = lp ? 4 : 8;
-  auto Fc_ = [&](int cc) { return (void*)((char*)c->F + cc * N * es); };
-  auto Dc_ = [&](int cc) { return (void*)((char*)c->D + cc * N * es); };
+  auto Fc_ = [&](int cc) { return (void*)((char*)b.F + cc * N * es); };
+  auto D2c_ = [&](int cc) { return (void*)((char*)b.D2 + cc * N * es); };
+  auto D3c_ = [&](int cc) { return (void*)((char*)b.D3 + cc * N * es); };
   // 1. G, F
-  SETD_TRY(compute_gf(c, u, gp, s));
+  SETD_TRY(compute_gf(c, u, gp, s, b.G, b.F));
   const int e21 = bank_index(SETD_STAGE_2, 1), e31 = bank_index(SETD_STAGE_3, 1), e32 = bank_index(SETD_STAGE_3, 2),
             ef1 = bank_index(SETD_STAGE_F, 1), ef2 = bank_index(SETD_STAGE_F, 2);
   const Splitting& S1 = c->sp[1];
@@ -381,7 +387,7 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
         int e;
         double mult;
         double* Y;
-      } tg[3] = {{e21, tau / 3.0, c->U2 + cc * N}, {e31, 2.0 * tau / 3.0, c->U3 + cc * N}, {ef1, tau, c->W + cc * N}};
+      } tg[3] = {{e21, tau / 3.0, b.U2 + cc * N}, {e31, 2.0 * tau / 3.0, b.U3 + cc * N}, {ef1, tau, c->W + cc * N}};
       for (int k = 0; k < 3; ++k) {
         TuckerOut& o = outs[no++];
         o.Y = tg[k].Y;
@@ -394,23 +400,23 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
     }
     SETD_TRY(run_tucker_group(d, c->dims, outs, no, prec, s));
   }
-  // 3. D = g(U2) - G
-  SETD_TRY(launch_stage_d(c->U2, c->G, nc, N, gp, c->D, tdt, s));
-  // 4. U3 += 4tau/3 S_2(2tau/3) D
+  // 3. D2 = g(U2) - G
+  SETD_TRY(launch_stage_d(b.U2, b.G, nc, N, gp, b.D2, tdt, s));
+  // 4. U3 += 4tau/3 S_2(2tau/3) D2
   {
     TuckerOut outs[2];
     for (int cc = 0; cc < nc; ++cc) {
       TuckerOut& o = outs[cc];
-      o.Y = c->U3 + cc * N;
-      o.base = c->U3 + cc * N;
+      o.Y = b.U3 + cc * N;
+      o.base = b.U3 + cc * N;
       o.nterms = T;
       for (int t = 0; t < T; ++t)
-        o.term[t] = {Dc_(cc), c->bank[cc][e32][t], 4.0 * tau / 3.0 * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
+        o.term[t] = {D2c_(cc), c->bank[cc][e32][t], 4.0 * tau / 3.0 * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
     SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s));
   }
-  // 5. D = g(U3) - G
-  SETD_TRY(launch_stage_d(c->U3, c->G, nc, N, gp, c->D, tdt, s));
+  // 5. D3 = g(U3) - G
+  SETD_TRY(launch_stage_d(b.U3, b.G, nc, N, gp, b.D3, tdt, s));
   // 6. U = W + 3tau/2 S_2(tau) D
   {
     TuckerOut outs[2];
@@ -420,11 +426,19 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
       o.base = c->W + cc * N;
       o.nterms = T;
       for (int t = 0; t < T; ++t)
-        o.term[t] = {Dc_(cc), c->bank[cc][ef2][t], 1.5 * tau * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
+        o.term[t] = {D3c_(cc), c->bank[cc][ef2][t], 1.5 * tau * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
     SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s));
   }
   return SETD_OK;
+}
+
+namespace {
+
+// The step of setd_etd_step: stage quantities in the context's buffers (D2
+// and D3 share one).
+int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
+  return step_with(c, u, gp, s, StageBufs{c->G, c->F, c->U2, c->D, c->U3, c->D});
 }
 
 // One etd2rkds step: U2 = U + tau T(F, {phi_1}), D = g(U2) - G,
@@ -901,6 +915,34 @@ int setd_etd_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, co
                   void* stream) {
   clear_error();
   return run_steps(c, u, nsteps, tau, g_kind, params, nparams, (hipStream_t)stream, step_once);
+}
+
+int setd_etd_step_record(setd_ctx* c, double* u, double tau, int g_kind, const double* params, int nparams,
+                         double* rec, void* stream) {
+  clear_error();
+  SETD_CHECK_ARG(c != nullptr, "ctx is NULL");
+  SETD_CHECK_ARG(u != nullptr && rec != nullptr, "u and rec must be non-NULL");
+  const int64_t NC = c->ncomp * c->N;
+  SETD_CHECK_ARG(!overlap(u, NC * 8, rec, 6 * NC * 8), "u and rec overlap");
+  SETD_CHECK_ARG(tau > 0.0, "tau must be positive");
+  if (!std::isfinite(tau)) {
+    set_error("tau is not finite");
+    return SETD_ENONFINITE;
+  }
+  if (c->prec != SETD_PREC_F64) {
+    set_error("the recorded step runs in FP64 only");
+    return SETD_EUNSUPPORTED;
+  }
+  GParams gp;
+  SETD_TRY(make_gparams(g_kind, params, nparams, c->ncomp, gp));
+  hipStream_t s = (hipStream_t)stream;
+  if (tau != c->tau) {
+    c->tau = tau;
+    SETD_TRY(build_bank(c, s));
+    drop_graph(c);
+  }
+  const StageBufs b{rec, rec + NC, rec + 2 * NC, rec + 3 * NC, rec + 4 * NC, rec + 5 * NC};
+  return step_with(c, u, gp, s, b);
 }
 
 int setd_etd2_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params, int nparams,

@@ -89,6 +89,8 @@ def test_validation_errors_before_any_launch():
     assert lib.setd_batch_create(ctypes.byref(h), 2, 2, bd, 2, BA, 0.01, _lib.PREC_F32,
                                  None) == _lib.SETD_EUNSUPPORTED
     assert lib.setd_batch_step(None, None, 1, 0, p, 0, None) == _lib.SETD_EINVAL
+    assert lib.setd_etd_step_record(None, None, 0.01, 0, p, 0, None, None) == _lib.SETD_EINVAL
+    assert lib.setd_etd_adjoint_step_recorded(None, None, None, None, 0, p, 0, 0, None, None) == _lib.SETD_EINVAL
     info = (ctypes.c_int64 * _lib.BATCH_INFO)()
     assert lib.setd_batch_info(None, info) == _lib.SETD_EINVAL
     assert lib.setd_batch_set_tiles(None, (ctypes.c_int * 6)(2, 2, 0, 2, 2, 0)) == _lib.SETD_EINVAL

@@ -157,3 +157,83 @@ def test_fhn128_200_steps_gradients_vs_central_differences():
             "" if fd_small is None else "   (h = 1e-6: %.10e, rel %.2e)" % (fd_small, abs(fd_small - ad) / abs(ad))))
     for name, fd, fd_small, ad, tol in checks:
         assert abs(fd - ad) <= tol * abs(fd), name
+
+
+@pytest.mark.parametrize("kind", ["fhn3d", "schnak2d", "dense"])
+def test_recorded_step_and_adjoint(kind):
+    """setd_etd_step_record: the same new state as setd_etd_step (bit for
+    bit), stage quantities G, F, U2, D2, U3, D3 equal to the oracle's (eq.
+    exprk3 with the split actions, composed here from the oracle's pieces),
+    and setd_etd_adjoint_step_recorded gives the oracle's gradients."""
+    import oracle
+    p, n = _small(kind)
+    T = torch()
+    ctx = setd.Context(p.dims, [[dev(M) for M in Ac] for Ac in p.A], p.tau)
+    N = int(np.prod(p.dims))
+    u_rec = T.from_numpy(_flat(p.U0)).cuda()
+    u_ref = u_rec.clone()
+    states = [u_rec.clone()]
+    recs = T.empty((n, 6 * 2 * N), dtype=T.float64, device="cuda")
+    for k in range(n):
+        ctx.step_record(u_rec, recs[k], p.g_kind, p.params)
+        ctx.step(u_ref, 1, p.g_kind, p.params)
+        states.append(u_rec.clone())
+    T.cuda.synchronize()
+    assert T.equal(u_rec, u_ref), (u_rec - u_ref).abs().max().item()
+    # stage quantities of the first step against the oracle
+    banks = oracle.make_banks(p.A, p.tau)
+    U = p.U0
+    G = oracle.reaction(p.g_kind, U, p.params)
+    F = [oracle.kron_sum_action(U[c], p.A[c]) + G[c] for c in range(2)]
+    U2 = [U[c] + p.tau / 3.0 * banks[c].split_apply(1, 2, F[c]) for c in range(2)]
+    G2 = oracle.reaction(p.g_kind, U2, p.params)
+    D2 = [G2[c] - G[c] for c in range(2)]
+    U3 = [U[c] + 2.0 * p.tau / 3.0 * banks[c].split_apply(1, 3, F[c])
+          + 4.0 * p.tau / 3.0 * banks[c].split_apply(2, 3, D2[c]) for c in range(2)]
+    G3 = oracle.reaction(p.g_kind, U3, p.params)
+    D3 = [G3[c] - G[c] for c in range(2)]
+    r0 = recs[0].cpu().numpy()
+    for q, (name, ref) in enumerate((("G", G), ("F", F), ("U2", U2), ("D2", D2), ("U3", U3), ("D3", D3))):
+        got = r0[q * 2 * N:(q + 1) * 2 * N]
+        e = rel_l2(got, _flat(ref))
+        say("  rec %s rel_l2 %.2e" % (name, e))
+        assert e < 1e-12, (name, e)
+    # adjoint through the recorded stages against the oracle's gradients
+    rng = np.random.default_rng(11)
+    target = [x + 0.1 * rng.standard_normal(x.shape) for x in p.U0]
+    L, U0bar, pbar, sig = oadj.loss_and_gradients(p.U0, p.A, p.tau, n, p.g_kind, p.params, target)
+    ubar = states[-1] - T.from_numpy(_flat(target)).cuda()
+    grad = T.zeros(len(p.params) + 2, dtype=T.float64, device="cuda")
+    for k in range(n - 1, -1, -1):
+        ctx.adjoint_step(states[k], ubar, p.g_kind, p.params, grad, sigma_mask=3, rec=recs[k])
+    T.cuda.synchronize()
+    e_u = rel_l2(ubar.cpu().numpy(), _flat(U0bar))
+    g = grad.cpu().numpy()
+    say("  recorded adjoint: ubar rel_l2 %.2e" % e_u)
+    assert e_u < TOL
+    assert np.all(np.abs(g[:len(p.params)] - pbar) <= TOL * np.max(np.abs(pbar)))
+    assert np.all(np.abs(g[len(p.params):] - sig) < TOL * np.abs(sig))
+
+
+def test_autograd_without_recording_matches_oracle():
+    """The checkpointed backward pass with record=False (the adjoint steps
+    recompute their stages) gives the same gradients."""
+    p, _ = _small("fhn3d")
+    n = 5
+    rng = np.random.default_rng(13)
+    target = [x + 0.1 * rng.standard_normal(x.shape) for x in p.U0]
+    L, U0bar, pbar, sig = oadj.loss_and_gradients(p.U0, p.A, p.tau, n, p.g_kind, p.params, target)
+    T = torch()
+    D = [[dev(wl.neumann_d2(m)) for m in p.dims] for _ in range(2)]
+    diff = T.tensor([p.A[0][0][1, 1] / wl.neumann_d2(p.dims[0])[1, 1],
+                     p.A[1][0][1, 1] / wl.neumann_d2(p.dims[0])[1, 1]], dtype=T.float64, requires_grad=True)
+    params = T.tensor(p.params, dtype=T.float64, requires_grad=True)
+    u0 = T.from_numpy(_flat(p.U0)).cuda().requires_grad_(True)
+    uT = sad.integrate(u0, params, diff, dims=p.dims, D=D, g_kind=p.g_kind, tau=p.tau, nsteps=n, checkpoint=2,
+                       record=False)
+    loss = 0.5 * ((uT - T.from_numpy(_flat(target)).cuda()) ** 2).sum()
+    loss.backward()
+    assert rel_l2(u0.grad.cpu().numpy(), _flat(U0bar)) < TOL
+    assert np.all(np.abs(params.grad.numpy() - pbar) <= TOL * np.max(np.abs(pbar)))
+    gd = diff.grad.numpy() * diff.detach().numpy()
+    assert np.all(np.abs(gd - sig) <= TOL * np.abs(sig))
