@@ -249,8 +249,10 @@ int build_adjoint_bank(setd_ctx* c, hipStream_t s) {
 int alloc_adjoint_buffers(setd_ctx* c) {
   const int64_t NN = (int64_t)c->ncomp * c->N;
   const size_t fb = round_up(NN * 8, 256);
+  const size_t cb = round_up(c->N * 8, 256);
   const int nfields = 11;
-  SETD_TRY(c->adj_mem.alloc(nfields * fb + (size_t)kRows * kRedBlocks * 8));
+  const int nchain = c->d == 3 ? c->ncomp * 9 * 2 : 0;   // sY: one field each
+  SETD_TRY(c->adj_mem.alloc(nfields * fb + nchain * cb + (size_t)kRows * kRedBlocks * 8));
   char* q = (char*)c->adj_mem.p;
   double** f[nfields] = {&c->aD2, &c->aD3, &c->Fbar, &c->Dbar, &c->Gbar, &c->U3bar,
                          &c->U2bar, &c->Ef, &c->E3, &c->E2, &c->KtF};
@@ -258,7 +260,75 @@ int alloc_adjoint_buffers(setd_ctx* c) {
     *f[k] = (double*)q;
     q += fb;
   }
+  if (nchain)
+    for (int cc = 0; cc < c->ncomp; ++cc)
+      for (int j = 0; j < 9; ++j)
+        for (int h = 0; h < 2; ++h) {
+          c->sY[cc][j][h] = (double*)q;
+          q += cb;
+        }
   c->part = (double*)q;
+  return SETD_OK;
+}
+
+// d = 3: E = sum_k sum_t s_t sum_mu T(V_k, {P_kt with mode mu -> dP_kt,mu})
+// for each chain (output k, term t) of one component, sharing the partial
+// products between the three derivative Tuckers of a term: with
+// X0 = V x1 P1, X1 = V x1 dP1 (mode 1), then X0 <- X0 x2 P2 and
+// X1 <- X1 x2 P2 + X0 x2 dP2 (mode 2), the sum is X1 x3 P3 + X0 x3 dP3
+// (mode 3): 7 mode products per term instead of 9.
+struct SigmaChain {
+  const double* V;
+  void* const* P;    // packed bank matrices of the term
+  void* const* dP;   // packed derivative matrices
+  double scale;
+  double* A0;        // mode-1 partials
+  double* A1;
+  double* B0;        // mode-2 partials
+  double* B1;
+};
+
+int sigma_chains_d3(const int* dims, SigmaChain* ch, int nch, double* const* E, const double* const* Ebase,
+                    int nout, int T, hipStream_t s) {
+  const int64_t N = (int64_t)dims[0] * dims[1] * dims[2];
+  std::vector<ModeJob> jobs;
+  for (int k = 0; k < nch; ++k) {
+    jobs.push_back(mk_job(ch[k].V, ch[k].P[0], 1.0, ch[k].A0, nullptr, 1, dims[0], N / dims[0]));
+    jobs.push_back(mk_job(ch[k].V, ch[k].dP[0], 1.0, ch[k].A1, nullptr, 1, dims[0], N / dims[0]));
+  }
+  SETD_TRY(launch_f64_jobs(jobs, true, s));
+  for (int k = 0; k < nch; ++k) {
+    jobs.push_back(mk_job(ch[k].A0, ch[k].P[1], 1.0, ch[k].B0, nullptr, dims[0], dims[1], dims[2]));
+    ModeJob jb = mk_job(ch[k].A1, ch[k].P[1], 1.0, ch[k].B1, nullptr, dims[0], dims[1], dims[2]);
+    jb.nterms = 2;
+    jb.X[1] = ch[k].A0;
+    jb.P[1] = ch[k].dP[1];
+    jb.scale[1] = 1.0;
+    jobs.push_back(jb);
+  }
+  SETD_TRY(launch_f64_jobs(jobs, false, s));
+  // mode 3: output o sums chains o*T .. o*T+T-1; first the X1 x3 P3 terms
+  // (onto Ebase[o], or none), then the X0 x3 dP3 terms onto E[o]
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int o = 0; o < nout; ++o) {
+      ModeJob jb{};
+      jb.nterms = T;
+      for (int t = 0; t < T; ++t) {
+        const SigmaChain& q = ch[o * T + t];
+        jb.X[t] = pass == 0 ? q.B1 : q.B0;
+        jb.P[t] = pass == 0 ? q.P[2] : q.dP[2];
+        jb.scale[t] = q.scale;
+      }
+      jb.Y = E[o];
+      jb.base = pass == 0 ? Ebase[o] : E[o];
+      jb.na = (int64_t)dims[0] * dims[1];
+      jb.nb = 1;
+      jb.n = dims[2];
+      jb.ldp = packed_ld(dims[2]);
+      jobs.push_back(jb);
+    }
+    SETD_TRY(launch_f64_jobs(jobs, false, s));
+  }
   return SETD_OK;
 }
 
@@ -322,7 +392,37 @@ int adjoint_step(setd_ctx* c, const double* u_in, const double* rec, double* uba
   // Ef = tau dS1(f) F + 3tau/2 dS2(f) D3, E3 = 2tau/3 dS1(3) F + 4tau/3 dS2(3) D2,
   // E2 = tau/3 dS1(2) F; dS V = sum_i eta_i sum_mu T(V, {P_i with P_{i,mu} -> dP_{i,mu}}).
   const bool dots = sigma_mask != 0;
-  if (dots) {
+  if (dots && d == 3) {
+    for (int a = 0; a < 2; ++a)
+      for (int cc = 0; cc < nc; ++cc) {
+        if (!(sigma_mask & (1 << cc))) continue;
+        struct {
+          double* E;
+          double* X;
+          int e;
+          double mult;
+          const double* eta;
+        } spec[3] = {
+            {c->Ef, a == 0 ? sF : sD3, a == 0 ? ef1 : ef2, a == 0 ? tau : 1.5 * tau, a == 0 ? eta1 : eta2},
+            {c->E3, a == 0 ? sF : sD2, a == 0 ? e31 : e32, a == 0 ? 2.0 * tau / 3.0 : 4.0 * tau / 3.0,
+             a == 0 ? eta1 : eta2},
+            {c->E2, sF, e21, tau / 3.0, eta1}};
+        const int nout = a == 0 ? 3 : 2;   // E2 has a phi_1 action only
+        SigmaChain ch[9];
+        double* E[3];
+        const double* Eb[3];
+        for (int k = 0; k < nout; ++k) {
+          E[k] = at(spec[k].E, cc);
+          Eb[k] = a == 0 ? nullptr : E[k];   // the first pass overwrites
+          for (int t = 0; t < T; ++t) {
+            const int j = k * T + t;
+            ch[j] = {at(spec[k].X, cc), c->bank[cc][spec[k].e][t], c->dbank[cc][spec[k].e][t],
+                     spec[k].mult * spec[k].eta[t], c->Y1[cc][j], c->Y2[cc][j], c->sY[cc][j][0], c->sY[cc][j][1]};
+          }
+        }
+        SETD_TRY(sigma_chains_d3(c->dims, ch, nout * T, E, Eb, nout, T, s));
+      }
+  } else if (dots) {
     void* mats[3][3][3];   // [output][term][mu]
     for (int a = 0; a < 2; ++a)
       for (int m0 = 0; m0 < d; ++m0) {

@@ -43,6 +43,7 @@ struct setd_ctx {
   void* ApkT[2][3] = {};          // transposed A (dense K path)
   double *aD2 = nullptr, *aD3 = nullptr, *Fbar = nullptr, *Dbar = nullptr, *Gbar = nullptr;
   double *U3bar = nullptr, *U2bar = nullptr, *Ef = nullptr, *E3 = nullptr, *E2 = nullptr, *KtF = nullptr;
+  double* sY[2][9][2] = {};   // d = 3: mode-2 partials of the diffusion-size derivative chains
   double* part = nullptr;         // per-block partial sums of the gradient reductions
   // exprk3ds_cplx (set up by its first step; rebuilt when tau changes)
   double cplx_tau = 0.0;
