@@ -195,6 +195,112 @@ __device__ __forceinline__ void mode1_tile(const ModeJob& jb, int64_t lt) {
   }
 }
 
+// Mode 1 with the matrix panel in LDS (interior jobs, 192 <= n <= 256,
+// 4 x 4 tiles).  A workgroup of 8 waves shares one 64-row panel of P, stored
+// in LDS in the order the MFMA reads it (chunk of 16 p, row m, lane: 4 p),
+// so no wave holds P in registers; each wave then computes `reps` 64 x 64
+// tiles of the workgroup's column group (8 * reps column tiles), reading X
+// in 32-byte runs per lane (whole cache lines) through a two-deep ring.
+// Workgroup w of a job: panel w % tiles_i, column group w / tiles_i.
+constexpr int kLdsWaves = 8;
+constexpr int kLdsMinN = 192, kLdsMaxN = 256;
+// Tiles per wave: 4 measured best at FHN 256^3 (mode 1 at 64.8 TFLOP/s
+// against 63.0 with 2, 52.3 with 6 and 58.2 for the register-only kernel);
+// below n = 192 the register-only kernel is faster (the panel fill weighs
+// more against a shorter contraction).
+constexpr int kLdsReps = 4;
+
+__global__ void __launch_bounds__(512, 1) mode1_lds_kernel(const ModeJobs J, int64_t per_xcd, int reps) {
+  __shared__ d4 panel[(kLdsMaxN / 16) * 4 * 64];   // 128 KB
+  const int64_t w = remap_xcd(blockIdx.x, per_xcd);
+  if (w >= J.total_tiles) return;   // uniform over the workgroup
+  const int j = find_job(J, w);
+  const ModeJob& jb = J.job[j];
+  const int64_t lw = w - jb.tile_begin;
+  const int it = (int)(lw % jb.tiles_i);
+  const int64_t bg = lw / jb.tiles_i;
+  const int n = jb.n, ldp = jb.ldp;
+  const int nchunk = n / 16;
+  const int i0 = it * 64;
+  const double* __restrict__ PT = (const double*)jb.P[0];
+  // fill: entry q = (c * 4 + m) * 64 + lane holds P[i0 + 4 l + m][16 c + 4 g + 0..3]
+  for (int q = threadIdx.x; q < nchunk * 256; q += 512) {
+    const int ln = q & 63, m = (q >> 6) & 3, c = q >> 8;
+    const int l = ln & 15, g = ln >> 4;
+    panel[q] = *(const d4*)(PT + (int64_t)(i0 + 4 * l + m) * ldp + 16 * c + 4 * g);
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  for (int rep = 0; rep < reps; ++rep) {
+  const int64_t bt = (bg * reps + rep) * kLdsWaves + wave;
+  if (bt >= jb.tiles_a) return;
+  const int lane = threadIdx.x & 63, g = lane >> 4, l = lane & 15;
+  const int64_t b0 = bt * 64;
+  const double* __restrict__ X = (const double*)jb.X[0];
+  const double* pb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) pb[u] = X + (b0 + 16 * u + l) * (int64_t)n + 4 * g;
+  d4 acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
+  auto load = [&](int c, d4* xr) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xr[u] = *(const d4*)(pb[u] + 16 * c);
+  };
+  auto mma = [&](int c, const d4* xr) {
+    d4 a[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a[m] = panel[(c * 4 + m) * 64 + lane];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[m][u] = mfma(a[m][jj], xr[u][jj], acc[m][u]);
+  };
+  d4 x0[4], x1[4];
+  load(0, x0);
+  for (int c = 0; c < nchunk; c += 2) {
+    load(c + 1, x1);                                 // nchunk is even (n % 32 == 0)
+    mma(c, x0);
+    load(c + 2 < nchunk ? c + 2 : c, x0);
+    mma(c + 1, x1);
+  }
+  // epilogue as in mode1_tile: lane (g, l) owns rows i0 + 4 g + 16 r + (0..3)
+  // of column b0 + 16 u + l
+  const double sc = jb.scale[0];
+  double* __restrict__ Y = (double*)jb.Y;
+  const double* __restrict__ base = (const double*)jb.base;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t col = (b0 + 16 * u + l) * (int64_t)n;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ir = i0 + 4 * g + 16 * r;
+      if (ir + 4 <= n) {
+#pragma unroll
+        for (int m = 0; m < 4; m += 2) {
+          d2 v = d2{acc[m][u][r], acc[m + 1][u][r]} * sc;
+          if (base) v += *(const d2*)(base + col + ir + m);
+          *(d2*)(Y + col + ir + m) = v;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if (ir + m < n) {
+            double v = acc[m][u][r] * sc;
+            if (base) v += base[col + ir + m];
+            Y[col + ir + m] = v;
+          }
+        }
+      }
+    }
+  }
+  }
+}
+
 // Job table in the kernel arguments (up to kMaxJobs outputs per launch).
 // Two waves per SIMD is the target occupancy: with that register budget the
 // accumulators stay in place through the k loop (a tighter default made the
@@ -509,6 +615,28 @@ int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
   ProfScope prof(s, kProfMode1F64, fl, by);
   int mode = 2;
   for (int j = 0; j < J.njobs; ++j) mode = std::min(mode, job_mode(J.job[j], true, cfg.tm, cfg.tn));
+  bool lds = mode == 2 && cfg.tm == 4 && cfg.tn == 4;
+  for (int j = 0; j < J.njobs; ++j)
+    lds = lds && J.job[j].n >= kLdsMinN && J.job[j].n <= kLdsMaxN && J.job[j].n % 32 == 0;
+  if (lds) {
+    // workgroups instead of tiles: per job tiles_i panels x column groups of
+    // 8 * reps tiles
+    const int reps = kLdsReps;
+    int64_t tot = 0;
+    for (int j = 0; j < J.njobs; ++j) {
+      ModeJob& jb = J.job[j];
+      jb.tile_begin = tot;
+      tot += (int64_t)jb.tiles_i * ceil_div(jb.tiles_a, kLdsWaves * reps);
+    }
+    J.total_tiles = tot;
+    J.tiles_per_job = J.njobs > 0 ? tot / J.njobs : 0;
+    for (int j = 0; j < J.njobs; ++j)
+      if (J.job[j].tile_begin != (int64_t)j * J.tiles_per_job) J.tiles_per_job = 0;
+    const int64_t per = ceil_div(tot, 8);
+    hipLaunchKernelGGL(mode1_lds_kernel, dim3((unsigned)(per * 8)), dim3(64 * kLdsWaves), 0, s, J, per, reps);
+    SETD_LAUNCHED();
+    return SETD_OK;
+  }
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
   SETD_LAUNCH_MODES(mode1_f64_kernel, 4, 4)

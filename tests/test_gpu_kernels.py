@@ -55,6 +55,27 @@ def test_tucker_all_modes(dims, alpha, beta):
     assert rel_err(host(Wd, dims), ref) < TOL
 
 
+@pytest.mark.parametrize("dims", [(256, 192), (224, 128), (192, 320), (256, 64, 3), (192, 64, 2)])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (0.7, 1.0)])
+def test_mode1_lds_panel_path(dims, alpha, beta):
+    """Mode-1 products on the LDS-panel path (192 <= n1 <= 256, n1 % 32 == 0,
+    a multiple of 64 columns): full and partial column groups (waves without
+    a tile), the epilogue with and without the FP64 base, the product's scale
+    (alpha folded into the last matrix); also inside a full Tucker."""
+    T = random_tensor(dims, 6)
+    W0 = random_tensor(dims, 7)
+    L = random_matrix(dims[0], 31, scale=0.3)
+    say("mode-1 LDS path", dims, alpha, beta)
+    Wd = dev(W0)
+    setd.tucker_apply(dev(T), Wd, dims, [dev(L)] + [None] * (len(dims) - 1), alpha=alpha, beta=beta)
+    ref = alpha * oracle.mode_product(T, L, 1) + beta * W0
+    assert rel_err(host(Wd, dims), ref) < TOL
+    Ls = [L] + [random_matrix(n, 40 + k, scale=0.3) for k, n in enumerate(dims[1:])]
+    Wd = dev(W0)
+    setd.tucker_apply(dev(T), Wd, dims, [dev(M) for M in Ls], alpha=alpha, beta=beta)
+    assert rel_err(host(Wd, dims), alpha * oracle.tucker(T, Ls) + beta * W0) < TOL
+
+
 def test_tucker_identity_modes_and_workspace():
     dims = (20, 30, 10)
     T = random_tensor(dims, 4)
