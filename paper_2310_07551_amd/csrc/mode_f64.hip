@@ -495,6 +495,96 @@ __device__ __forceinline__ void modeB_tile(const ModeJob& jb, int64_t lt) {
   }
 }
 
+// Modes >= 2 with the matrix panel in LDS (interior single-term jobs,
+// 192 <= n <= 256, n % 64 == 0, 4 x 4 tiles).  A workgroup of 8 waves shares
+// one 64-column panel of P (times the job's scale), stored in LDS in the
+// order the MFMA reads it (k-step, lane: 4 columns); each wave computes
+// `reps` 64 a x 64 i tiles of the workgroup's group of (a-block, slab) pairs,
+// reading X in 32-byte runs per lane through a two-deep ring of 4-k-step
+// blocks.  (Multi-term jobs stay on the register kernel: refilling the panel
+// for every term cost more than it saved.)
+// Workgroup w of a job: panel w % tiles_i, group w / tiles_i of 8 * reps
+// (a-block, slab) pairs, pair q = a-block q % tiles_a, slab q / tiles_a.
+__global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int64_t per_xcd, int reps) {
+  __shared__ d4 panel[(kLdsMaxN / 4) * 64];   // 128 KB
+  const int64_t w = remap_xcd(blockIdx.x, per_xcd);
+  if (w >= J.total_tiles) return;   // uniform over the workgroup
+  const ModeJob& jb = J.job[find_job(J, w)];
+  const int64_t lw = w - jb.tile_begin;
+  const int it = (int)(lw % jb.tiles_i);
+  const int64_t grp = lw / jb.tiles_i;
+  const int n = jb.n, ldp = jb.ldp;
+  const int64_t na = jb.na;
+  const int64_t npairs = (int64_t)jb.tiles_a * jb.nb;
+  const int i0 = it * 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, l = lane & 15;
+  // fill: entry q = kk * 64 + lane' holds sc * P[i0 + 4 l' + 0..3][4 kk + g']
+  {
+    const double* __restrict__ P = (const double*)jb.P[0];
+    const double sc = jb.scale[0];
+    for (int q = threadIdx.x; q < (n / 4) * 64; q += 512) {
+      const int ln = q & 63, kk = q >> 6;
+      panel[q] = *(const d4*)(P + i0 + 4 * (ln & 15) + (int64_t)ldp * (4 * kk + (ln >> 4))) * sc;
+    }
+  }
+  __syncthreads();
+  constexpr int KB = 4;
+  for (int rep = 0; rep < reps; ++rep) {
+    const int64_t q = (grp * reps + rep) * kLdsWaves + wave;
+    if (q >= npairs) return;   // no barrier follows
+    const int64_t at = q % jb.tiles_a, b = q / jb.tiles_a;
+    const int64_t a0 = at * 64, arow = a0 + 4 * l;
+    const int64_t slab = na * (int64_t)n * b;
+    d4 acc[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
+    {
+      const double* __restrict__ xb = (const double*)jb.X[0] + slab + arow + na * g;
+      auto loadblk = [&](int p0, d4* xr) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) xr[k] = *(const d4*)(xb + na * (int64_t)(p0 + 4 * k));
+      };
+      auto mmablk = [&](int p0, const d4* xr) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          const d4 pv = panel[(p0 / 4 + k) * 64 + lane];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc[m][u] = mfma(xr[k][m], pv[u], acc[m][u]);
+        }
+      };
+      d4 xa[KB], xq[KB];
+      loadblk(0, xa);
+      for (int p0 = 0; p0 < n; p0 += 8 * KB) {   // n % 32 == 0
+        loadblk(p0 + 4 * KB, xq);
+        mmablk(p0, xa);
+        loadblk(p0 + 8 * KB < n ? p0 + 8 * KB : p0, xa);
+        mmablk(p0 + 4 * KB, xq);
+      }
+    }
+    // epilogue as in modeB_tile (TM = TN = 4, every row and column in range)
+    double* __restrict__ Y = (double*)jb.Y;
+    const double* __restrict__ base = (const double*)jb.base;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t off = slab + na * (int64_t)(i0 + 4 * l + u);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t ar = a0 + 4 * g + 16 * r;
+#pragma unroll
+        for (int m = 0; m < 4; m += 2) {
+          d2 v = d2{acc[m][u][r], acc[m + 1][u][r]};
+          if (base) v += *(const d2*)(base + off + ar + m);
+          *(d2*)(Y + off + ar + m) = v;
+        }
+      }
+    }
+  }
+}
+
 template <int TM, int TN, int MODE>
 __global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t per_xcd) {
   const int64_t t = remap_xcd(blockIdx.x, per_xcd);
@@ -657,6 +747,33 @@ int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
   ProfScope prof(s, kProfModeBF64, fl, by);
   int mode = 2;
   for (int j = 0; j < J.njobs; ++j) mode = std::min(mode, job_mode(J.job[j], false, cfg.tm, cfg.tn));
+  bool lds = mode == 2 && cfg.tm == 4;
+  for (int j = 0; j < J.njobs; ++j) {
+    const ModeJob& jb = J.job[j];
+    lds = lds && jb.nterms == 1 && jb.n >= kLdsMinN && jb.n <= kLdsMaxN && jb.n % 64 == 0 && jb.na % 64 == 0;
+  }
+  if (lds) {
+    // workgroups: per job n / 64 panels x groups of 8 * reps (a-block, slab)
+    // pairs; 4 tiles per wave as in mode 1 (measured at FHN 256^3: the
+    // single-term launches go from 62.6 to 65.3 TFLOP/s)
+    const int reps = kLdsReps;
+    int64_t tot = 0;
+    for (int j = 0; j < J.njobs; ++j) {
+      ModeJob& jb = J.job[j];
+      jb.tiles_i = jb.n / 64;
+      jb.tiles_a = (int)(jb.na / 64);
+      jb.tile_begin = tot;
+      tot += (int64_t)jb.tiles_i * ceil_div((int64_t)jb.tiles_a * jb.nb, (int64_t)kLdsWaves * reps);
+    }
+    J.total_tiles = tot;
+    J.tiles_per_job = J.njobs > 0 ? tot / J.njobs : 0;
+    for (int j = 0; j < J.njobs; ++j)
+      if (J.job[j].tile_begin != (int64_t)j * J.tiles_per_job) J.tiles_per_job = 0;
+    const int64_t per = ceil_div(tot, 8);
+    hipLaunchKernelGGL(modeB_lds_kernel, dim3((unsigned)(per * 8)), dim3(64 * kLdsWaves), 0, s, J, per, reps);
+    SETD_LAUNCHED();
+    return SETD_OK;
+  }
   const int64_t per = ceil_div(J.total_tiles, 8);
   const dim3 grid((unsigned)(per * 8));
   SETD_LAUNCH_MODES(modeB_f64_kernel, 4, 4)

@@ -80,6 +80,19 @@ def test_fhn_128_steps():
     _assert_close(_run_gpu(prob, 6), _run_oracle(prob, 6))
 
 
+@pytest.mark.parametrize("dims", [(16, 8, 192), (64, 192, 3), (192, 64, 4)])
+def test_lds_panel_paths(dims):
+    """Grids whose mode products take the LDS-panel kernels: a last mode of
+    192 (three-term jobs, the panel refilled per term), a middle mode of 192
+    with 64 rows per slab (single-term jobs, several tiles per wave), a first
+    mode of 192.  (A 256-point last mode on a thin grid sits at 1.7e-12 after
+    three steps with every kernel: the phi matrices of that stiff direction
+    carry about u times their norm.)"""
+    prob = wl.fhn_3d(dims=dims)
+    say("lds panel paths", dims)
+    _assert_close(_run_gpu(prob, 2), _run_oracle(prob, 2))
+
+
 @pytest.mark.parametrize("case", ["fhn_ragged", "schnak_ragged", "fhn_nonsquare", "schnak_rect"])
 def test_ragged_grids(case):
     if case == "fhn_ragged":

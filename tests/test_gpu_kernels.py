@@ -76,6 +76,30 @@ def test_mode1_lds_panel_path(dims, alpha, beta):
     assert rel_err(host(Wd, dims), alpha * oracle.tucker(T, Ls) + beta * W0) < TOL
 
 
+@pytest.mark.parametrize("dims,mu", [((64, 256, 2), 2), ((128, 192, 3), 2), ((64, 5, 256), 3), ((64, 192), 2)])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (0.7, 1.0)])
+def test_modeB_lds_panel_path(dims, mu, alpha, beta):
+    """A single mode product along mode mu >= 2 on the LDS-panel path
+    (192 <= n <= 256, n % 64 == 0, a multiple of 64 rows per slab): several
+    slabs per workgroup group, partial groups, with and without the FP64
+    base; also inside a full Tucker."""
+    T = random_tensor(dims, 8)
+    W0 = random_tensor(dims, 9)
+    L = random_matrix(dims[mu - 1], 33, scale=0.3)
+    mats = [None] * len(dims)
+    mats[mu - 1] = dev(L)
+    say("modes>=2 LDS path", dims, mu, alpha, beta)
+    Wd = dev(W0)
+    setd.tucker_apply(dev(T), Wd, dims, mats, alpha=alpha, beta=beta)
+    ref = alpha * oracle.mode_product(T, L, mu) + beta * W0
+    assert rel_err(host(Wd, dims), ref) < TOL
+    Ls = [random_matrix(nn, 50 + k, scale=0.3) for k, nn in enumerate(dims)]
+    Ls[mu - 1] = L
+    Wd = dev(W0)
+    setd.tucker_apply(dev(T), Wd, dims, [dev(M) for M in Ls], alpha=alpha, beta=beta)
+    assert rel_err(host(Wd, dims), alpha * oracle.tucker(T, Ls) + beta * W0) < TOL
+
+
 def test_tucker_identity_modes_and_workspace():
     dims = (20, 30, 10)
     T = random_tensor(dims, 4)
