@@ -339,12 +339,14 @@ int setd_field_norms(const double* x, const double* y, int64_t n, double* out, v
  *   0 mode-1 products, FP64          1 modes >= 2 products, FP64
  *   2 mode-1 products, FP32/BF16x3   3 modes >= 2 products, FP32/BF16x3
  *   4 pointwise (G/F, stage differences)
+ *   5 modes >= 2 products, FP64, matrix panel in LDS (single-term jobs with
+ *     192 <= n <= 256)
  * setd_profile_read synchronises the recorded events and writes, per class
  * c, out[4c..4c+3] = {launches, total milliseconds, total flops, total bytes}
  * (out is host memory of SETD_PROF_CLASSES*4 doubles); reset != 0 clears the
  * record.  Enabling costs one event pair per launch.
  */
-#define SETD_PROF_CLASSES 5
+#define SETD_PROF_CLASSES 6
 int setd_profile_enable(int on);
 int setd_profile_read(double* out, int reset);
 

@@ -69,7 +69,7 @@ SIGNATURES = {
 
 BATCH_INFO = 10
 
-PROF_CLASSES = ("mode1_f64", "modeB_f64", "mode1_lp", "modeB_lp", "pointwise")
+PROF_CLASSES = ("mode1_f64", "modeB_f64", "mode1_lp", "modeB_lp", "pointwise", "modeB_panel_f64")
 
 _lib = None
 

@@ -118,7 +118,14 @@ __device__ __forceinline__ int find_job_list(const int64_t* begins, int njobs, i
 enum class DType : int { F64 = 0, F32 = 1 };
 
 // ---- kernel timing (setd_profile_*), implemented in setd_api.hip ----
-enum ProfClass : int { kProfMode1F64 = 0, kProfModeBF64 = 1, kProfMode1LP = 2, kProfModeBLP = 3, kProfPointwise = 4 };
+enum ProfClass : int {
+  kProfMode1F64 = 0,
+  kProfModeBF64 = 1,
+  kProfMode1LP = 2,
+  kProfModeBLP = 3,
+  kProfPointwise = 4,
+  kProfModeBPanelF64 = 5   // modes >= 2, matrix panel in LDS
+};
 bool prof_on();
 // Records the begin event on construction and the end event on destruction
 // (only while profiling is enabled).

@@ -744,7 +744,6 @@ int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
   if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
   if (prof_on()) job_work(J, 8, 8, 8, fl, by);
-  ProfScope prof(s, kProfModeBF64, fl, by);
   int mode = 2;
   for (int j = 0; j < J.njobs; ++j) mode = std::min(mode, job_mode(J.job[j], false, cfg.tm, cfg.tn));
   bool lds = mode == 2 && cfg.tm == 4;
@@ -752,6 +751,8 @@ int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
     const ModeJob& jb = J.job[j];
     lds = lds && jb.nterms == 1 && jb.n >= kLdsMinN && jb.n <= kLdsMaxN && jb.n % 64 == 0 && jb.na % 64 == 0;
   }
+  // the two kernels are timed as separate classes
+  ProfScope prof(s, lds ? kProfModeBPanelF64 : kProfModeBF64, fl, by);
   if (lds) {
     // workgroups: per job n / 64 panels x groups of 8 * reps (a-block, slab)
     // pairs; 4 tiles per wave as in mode 1 (measured at FHN 256^3: the
