@@ -362,8 +362,10 @@ __device__ __forceinline__ void modeB_tile(const ModeJob& jb, int64_t lt) {
 
     if constexpr (fast) {
       // Interior tile: blocks of KB k-steps (4 KB values of p) in ping-pong
-      // registers; the scale is applied to the matrix operand at use.
-      constexpr int KB = 4;
+      // registers; the scale is applied to the matrix operand at use.  A
+      // 4 x 4 tile takes blocks of 2, so that its ring fits beside the 128
+      // accumulator registers at two waves per SIMD.
+      constexpr int KB = (TM == 4 && TN == 4) ? 2 : 4;
       auto loadblk = [&](int p0, double (*xr)[TM], double (*pr)[TN]) {
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
@@ -585,8 +587,10 @@ __global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int
   }
 }
 
+// Two waves per SIMD, as for mode 1 (with it the 4 x 4 tile fits in 232
+// registers).
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) modeB_f64_kernel(const ModeJobs J, int64_t per_xcd) {
+__global__ void __launch_bounds__(64, 2) modeB_f64_kernel(const ModeJobs J, int64_t per_xcd) {
   const int64_t t = remap_xcd(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;
   const int j = find_job(J, t);
@@ -738,8 +742,12 @@ int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
 }
 
 int launch_modeB_f64(ModeJobs& J, hipStream_t s) {
-  // default from a sweep on MI355X (FHN 128^3 and 256^3): 4 x 2 tiles
-  const TileCfg cfg = env_tile("SETD_TILE_MODEB", TileCfg{4, 2});
+  // default tiles from sweeps on MI355X: 4 x 4 when every contraction is
+  // long (n >= 192; FHN 256^3 last mode 68.4 against 64.2 TFLOP/s for 4 x 2),
+  // 4 x 2 otherwise (FHN 128^3: 48.0 against 45.1; fewer, shorter tiles)
+  bool long_k = true;
+  for (int j = 0; j < J.njobs; ++j) long_k = long_k && J.job[j].n >= kLdsMinN;
+  const TileCfg cfg = env_tile("SETD_TILE_MODEB", long_k ? TileCfg{4, 4} : TileCfg{4, 2});
   finish_tiles(J, false, cfg.tm, cfg.tn);
   if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
