@@ -598,7 +598,7 @@ __global__ void __launch_bounds__(64, 2) modeB_f64_kernel(const ModeJobs J, int6
 }
 
 template <int TM, int TN, int MODE>
-__global__ void __launch_bounds__(64) modeB_f64_list_kernel(const ModeJob* __restrict__ jobs,
+__global__ void __launch_bounds__(64, 2) modeB_f64_list_kernel(const ModeJob* __restrict__ jobs,
                                                             const int64_t* __restrict__ begins, int njobs,
                                                             int64_t total, int64_t per_xcd) {
   for (int64_t raw = blockIdx.x; raw < 8 * per_xcd; raw += gridDim.x) {
