@@ -700,15 +700,24 @@ void job_work(const ModeJobs& J, int es_in, int es_out, int es_mat, double& flop
 
 int launch_mode1_f64(ModeJobs& J, hipStream_t s) {
   // default from a sweep on MI355X at FHN 256^3 (two waves per SIMD):
-  // 4 x 4 53.7, 2 x 4 43.7, 4 x 2 42.2, 2 x 2 34.3 TFLOP/s
-  const TileCfg cfg = env_tile("SETD_TILE_MODE1", TileCfg{4, 4});
+  // 4 x 4 53.7, 2 x 4 43.7, 4 x 2 42.2, 2 x 2 34.3 TFLOP/s.  Only the
+  // interior variant of the 4 x 4 tile fits the two-wave register budget
+  // (its 2-p ring); jobs that need the checked variants take 4 x 2 tiles,
+  // which do not spill.
+  auto min_mode = [&](int tm, int tn) {
+    int m = 2;
+    for (int j = 0; j < J.njobs; ++j) m = std::min(m, job_mode(J.job[j], true, tm, tn));
+    return m;
+  };
+  TileCfg def{4, 4};
+  if (min_mode(4, 4) < 2) def = TileCfg{4, 2};
+  const TileCfg cfg = env_tile("SETD_TILE_MODE1", def);
   finish_tiles(J, true, cfg.tm, cfg.tn);
   if (J.total_tiles == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
   if (prof_on()) job_work(J, 8, 8, 8, fl, by);
   ProfScope prof(s, kProfMode1F64, fl, by);
-  int mode = 2;
-  for (int j = 0; j < J.njobs; ++j) mode = std::min(mode, job_mode(J.job[j], true, cfg.tm, cfg.tn));
+  const int mode = min_mode(cfg.tm, cfg.tn);
   bool lds = mode == 2 && cfg.tm == 4 && cfg.tn == 4;
   for (int j = 0; j < J.njobs; ++j)
     lds = lds && J.job[j].n >= kLdsMinN && J.job[j].n <= kLdsMaxN && J.job[j].n % 32 == 0;
