@@ -8,8 +8,13 @@
 //  2. The diagonal [m/m] Pade approximant of phi_p at Y, m = 8:
 //       D(z) = sum_j d_j z^j,  d_j = (-1)^j m! (2m+p-j)! / ((2m+p)! j! (m-j)!),
 //       N(z) = sum_i n_i z^i,  n_i = sum_{j<=i} d_j / (p+i-j)!,
-//     so that D phi_p - N = O(z^{2m+1}); phi_p(Y) ~ D(Y)^{-1} N(Y) by a
-//     batched LU solve with partial pivoting.
+//     so that D phi_p - N = O(z^{2m+1}); phi_p(Y) ~ D(Y)^{-1} N(Y).
+//     D(Y)^{-1} comes from the Newton-Schulz iteration X <- X (2I - D X),
+//     whose residual I - D X squares at every step.  Because ||Y||_1 <= 1,
+//     ||I - D(Y)||_1 <= sum_{j>=1} |d_j| = rho (0.64 for p = 0, smaller for
+//     larger p), so X_0 = I reaches rounding level after a fixed, small
+//     number of steps, each two batched GEMMs on all compute units (a
+//     pivoted LU keeps one block per matrix busy for n sequential steps).
 //  3. Lower orders by the recurrence phi_k(Y) = Y phi_{k+1}(Y) + I/k!.
 //  4. s modified squarings
 //       phi_0(2Y) = phi_0(Y)^2,
@@ -38,9 +43,10 @@ struct GemmDesc {
   double* C;
 };
 
-// C = A B + diag_add * I for n x n column-major matrices, one descriptor per
-// blockIdx.z.  64 x 64 tile per 256-thread block, 4 x 4 per thread.
-__global__ void __launch_bounds__(256) gemm_nn_kernel(const GemmDesc* __restrict__ descs, int n, double diag_add) {
+// C = alpha A B + diag_add * I for n x n column-major matrices, one
+// descriptor per blockIdx.z; C must not overlap A or B.  64 x 64 tile per 256-thread block, 4 x 4 per thread.
+__global__ void __launch_bounds__(256) gemm_nn_kernel(const GemmDesc* __restrict__ descs, int n, double alpha,
+                                                          double diag_add) {
   const GemmDesc dsc = descs[blockIdx.z];
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
@@ -74,7 +80,7 @@ __global__ void __launch_bounds__(256) gemm_nn_kernel(const GemmDesc* __restrict
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) {
       const int r = m0 + tx + 16 * i, c = n0 + ty + 16 * j;
-      if (r < n && c < n) dsc.C[r + (int64_t)n * c] = acc[i][j] + (r == c ? diag_add : 0.0);
+      if (r < n && c < n) dsc.C[r + (int64_t)n * c] = alpha * acc[i][j] + (r == c ? diag_add : 0.0);
     }
 }
 
@@ -118,7 +124,9 @@ struct Coefs {
   double d[kPadeM + 1];
 };
 
-// N = sum n_i Y^i, D = sum d_i Y^i (Y^0 = I); Ypow[k-1] holds Y^k.
+// N = sum n_i Y^i, D = sum d_i Y^i (Y^0 = I); Ypow[k-1] holds Y^k.  Also
+// writes the first Newton-Schulz iterate X_1 = 2I - D over Y^2 (Ypow[1]),
+// which is not read again.
 __global__ void pade_combo_kernel(double* __restrict__ W, int n, int64_t stride, Coefs cf) {
   const int64_t nn = (int64_t)n * n;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -133,86 +141,7 @@ __global__ void pade_combo_kernel(double* __restrict__ W, int n, int64_t stride,
   }
   w[(int64_t)kPadeM * nn + idx] = sn;        // N
   w[(int64_t)(kPadeM + 1) * nn + idx] = sd;  // D
-}
-
-// Solve D X = N in place (X overwrites N), one 1024-thread block per entry;
-// Gaussian elimination with partial pivoting, then back substitution.
-__global__ void __launch_bounds__(1024) lu_solve_kernel(double* __restrict__ W, int n, int64_t stride) {
-  const int64_t nn = (int64_t)n * n;
-  double* Nm = W + stride * blockIdx.x + (int64_t)kPadeM * nn;
-  double* D = Nm + nn;
-  __shared__ double rv[1024];
-  __shared__ int ri[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += nt) {
-      const double v = fabs(D[i + (int64_t)n * k]);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
-    }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        const double o = rv[tid + w];
-        const int oi = ri[tid + w];
-        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) {
-          rv[tid] = o;
-          ri[tid] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int piv = ri[0];
-    __syncthreads();
-    if (piv != k) {
-      for (int j = tid; j < 2 * n; j += nt) {
-        double* M = j < n ? D : Nm;
-        const int c = j < n ? j : j - n;
-        if (j < n && c < k) continue;
-        const double t = M[k + (int64_t)n * c];
-        M[k + (int64_t)n * c] = M[piv + (int64_t)n * c];
-        M[piv + (int64_t)n * c] = t;
-      }
-    }
-    __syncthreads();
-    const double pivot = D[k + (int64_t)n * k];
-    for (int i = k + 1 + tid; i < n; i += nt) D[i + (int64_t)n * k] /= pivot;
-    __syncthreads();
-    const int rows = n - k - 1;
-    if (rows > 0) {
-      const int64_t tot = (int64_t)rows * (rows + n);
-      for (int64_t e = tid; e < tot; e += nt) {
-        const int i = k + 1 + (int)(e % rows);
-        const int jj = (int)(e / rows);
-        const double l = D[i + (int64_t)n * k];
-        if (jj < rows) {
-          const int j = k + 1 + jj;
-          D[i + (int64_t)n * j] -= l * D[k + (int64_t)n * j];
-        } else {
-          const int j = jj - rows;
-          Nm[i + (int64_t)n * j] -= l * Nm[k + (int64_t)n * j];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    const double dk = D[k + (int64_t)n * k];
-    for (int j = tid; j < n; j += nt) Nm[k + (int64_t)n * j] /= dk;
-    __syncthreads();
-    const int64_t tot = (int64_t)k * n;
-    for (int64_t e = tid; e < tot; e += nt) {
-      const int i = (int)(e % k), j = (int)(e / k);
-      Nm[i + (int64_t)n * j] -= D[i + (int64_t)n * k] * Nm[k + (int64_t)n * j];
-    }
-    __syncthreads();
-  }
+  w[nn + idx] = (diag ? 2.0 : 0.0) - sd;      // X_1
 }
 
 // Modified squaring combination for one entry and all orders at once:
@@ -275,6 +204,7 @@ int phi_batch(const double* A, int n, const double* c, int nentries, int p, doub
 
   // Pade coefficients (long double, from the closed forms above).
   Coefs cf;
+  int ns_iters = 0;
   {
     auto fact = [](int k) {
       long double f = 1.0L;
@@ -294,14 +224,27 @@ int phi_batch(const double* A, int n, const double* c, int nentries, int p, doub
       cf.n[i] = (double)nc[i];
       cf.d[i] = (double)d[i];
     }
+    long double rho = 0.0L;
+    for (int j = 1; j <= m; ++j) rho += fabsl(d[j]);
+    // residual bound after X_1 and `ns_iters` further steps: rho^(2^(ns_iters+1))
+    long double r = rho * rho;
+    while (r > 1e-22L && ns_iters < 12) {
+      r *= r;
+      ++ns_iters;
+    }
+    if (!(rho < 0.9L) || r > 1e-22L) {
+      set_error("phi: Pade denominator bound %g too large for the inverse iteration", (double)rho);
+      return SETD_EINVAL;
+    }
   }
 
   Buf ws, dev;
   SETD_HIP(hipMalloc(&ws.p, (size_t)chunk * stride * sizeof(double)));
   // per chunk: scalars (chunk) + gemm descriptors
-  // descriptors: (m-1) power products, p recurrence products and two
-  // parities of (p+1) squaring products, per entry
-  const int ndesc_max = chunk * ((kPadeM - 1) + p + 2 * (p + 1));
+  // descriptors: (m-1) power products, two parities of the two Newton-Schulz
+  // products, the final D^{-1} N, p recurrence products and two parities of
+  // (p+1) squaring products, per entry
+  const int ndesc_max = chunk * ((kPadeM - 1) + 5 + p + 2 * (p + 1));
   const size_t scal_bytes = ((chunk * sizeof(double) + 63) / 64) * 64;
   const size_t dev_bytes = scal_bytes + (size_t)ndesc_max * sizeof(GemmDesc);
   SETD_HIP(hipMalloc(&dev.p, dev_bytes));
@@ -332,6 +275,19 @@ int phi_batch(const double* A, int n, const double* c, int nentries, int p, doub
     GemmDesc* pow_d = hd + nd;
     for (int k = 2; k <= kPadeM; ++k)
       for (int j = 0; j < E; ++j) hd[nd++] = {blk(j, k - 2), blk(j, 0), blk(j, k - 1)};
+    // Newton-Schulz on the free power blocks: X in block 1 or 3 by parity,
+    // S = 2I - D X in block 2; then bufA[p] = X N
+    const int kD = kPadeM + 1, kN = kPadeM;
+    GemmDesc* ns_d[2][2];
+    for (int par = 0; par < 2; ++par) {
+      const int xi = par == 0 ? 1 : 3, xo = par == 0 ? 3 : 1;
+      ns_d[par][0] = hd + nd;
+      for (int j = 0; j < E; ++j) hd[nd++] = {blk(j, kD), blk(j, xi), blk(j, 2)};
+      ns_d[par][1] = hd + nd;
+      for (int j = 0; j < E; ++j) hd[nd++] = {blk(j, xi), blk(j, 2), blk(j, xo)};
+    }
+    GemmDesc* fin_d = hd + nd;
+    for (int j = 0; j < E; ++j) hd[nd++] = {blk(j, ns_iters % 2 == 0 ? 1 : 3), blk(j, kN), blk(j, offA + p)};
     // recurrence: bufA[k] = Y bufA[k+1] + I/k!
     GemmDesc* rec_d = hd + nd;
     for (int k = p - 1; k >= 0; --k)
@@ -359,16 +315,22 @@ int phi_batch(const double* A, int n, const double* c, int nentries, int p, doub
     // 2. powers
     for (int k = 2; k <= kPadeM; ++k) {
       hipLaunchKernelGGL(gemm_nn_kernel, dim3(gtile.x, gtile.y, E), dim3(256), 0, s, dptr(pow_d + (k - 2) * E), n,
+                         1.0, 0.0);
+      SETD_LAUNCHED();
+    }
+    // 3. N, D, X_1 = 2I - D; Newton-Schulz steps; phi_p(Y) ~ X N
+    hipLaunchKernelGGL(pade_combo_kernel, ew, dim3(256), 0, s, ws.p, n, stride, cf);
+    SETD_LAUNCHED();
+    for (int it = 0; it < ns_iters; ++it) {
+      hipLaunchKernelGGL(gemm_nn_kernel, dim3(gtile.x, gtile.y, E), dim3(256), 0, s, dptr(ns_d[it & 1][0]), n, -1.0,
+                         2.0);
+      SETD_LAUNCHED();
+      hipLaunchKernelGGL(gemm_nn_kernel, dim3(gtile.x, gtile.y, E), dim3(256), 0, s, dptr(ns_d[it & 1][1]), n, 1.0,
                          0.0);
       SETD_LAUNCHED();
     }
-    // 3. N, D and the solve: phi_p(Y) ~ D^{-1} N
-    hipLaunchKernelGGL(pade_combo_kernel, ew, dim3(256), 0, s, ws.p, n, stride, cf);
+    hipLaunchKernelGGL(gemm_nn_kernel, dim3(gtile.x, gtile.y, E), dim3(256), 0, s, dptr(fin_d), n, 1.0, 0.0);
     SETD_LAUNCHED();
-    hipLaunchKernelGGL(lu_solve_kernel, dim3(E), dim3(1024), 0, s, ws.p, n, stride);
-    SETD_LAUNCHED();
-    for (int j = 0; j < E; ++j)
-      SETD_HIP(hipMemcpyAsync(blk(j, offA + p), blk(j, kPadeM), nn * sizeof(double), hipMemcpyDeviceToDevice, s));
     // 4. phi_k = Y phi_{k+1} + I/k!
     {
       std::vector<double> invf(p + 1, 1.0);
@@ -376,7 +338,7 @@ int phi_batch(const double* A, int n, const double* c, int nentries, int p, doub
       for (int q = 0; q < p; ++q) {
         const int k = p - 1 - q;
         hipLaunchKernelGGL(gemm_nn_kernel, dim3(gtile.x, gtile.y, E), dim3(256), 0, s, dptr(rec_d + q * E), n,
-                           invf[k]);
+                           1.0, invf[k]);
         SETD_LAUNCHED();
       }
     }
@@ -384,7 +346,7 @@ int phi_batch(const double* A, int n, const double* c, int nentries, int p, doub
     int cur = 0;   // 0: current values in bufA, 1: in bufB
     for (int it = 0; it < sq; ++it) {
       hipLaunchKernelGGL(gemm_nn_kernel, dim3(gtile.x, gtile.y, E * (p + 1)), dim3(256), 0, s, dptr(sq_d[cur]), n,
-                         0.0);
+                         1.0, 0.0);
       SETD_LAUNCHED();
       const int64_t off_old = (int64_t)(cur == 0 ? offA : offB) * nn;
       const int64_t off_T = (int64_t)(cur == 0 ? offB : offA) * nn;
