@@ -148,7 +148,8 @@ def _phi_tol(X):
     return 1e-13 + 4.4e-16 * np.abs(X).sum(0).max()
 
 
-@pytest.mark.parametrize("n,c", [(1, 0.3), (5, 0.0), (9, 1e-3), (33, 0.05), (64, 2.0), (128, 0.5), (256, 0.67)])
+@pytest.mark.parametrize("n,c", [(1, 0.3), (5, 0.0), (9, 1e-3), (33, 0.05), (64, 2.0), (128, 0.5), (256, 0.67),
+                                 (512, 0.1), (1000, 0.02)])
 def test_phi_matrices_neumann(n, c):
     A = neumann_d2(max(n, 2))[:n, :n] * 42.1 if n > 1 else np.array([[-3.0]])
     say("phi", n, c)
@@ -168,6 +169,20 @@ def test_phi_matrices_general(n, scale):
         for k in range(ell + 1):
             G = got[k].reshape(n, n, order="F")
             assert rel_err(G, ref[k]) < _phi_tol(A) * 10, (n, ell, k, rel_err(G, ref[k]))
+
+
+@pytest.mark.parametrize("n,norm", [(16, 1 - 1e-12), (96, 0.999), (200, 1 - 1e-12)])
+def test_phi_matrices_at_the_scaling_threshold(n, norm):
+    """||X||_1 at the scaling threshold 1, where no squaring is applied and the
+    bound on ||I - D(X)||_1 that fixes the number of inverse-iteration steps
+    is reached; non-normal X, all orders up to 4."""
+    A = random_matrix(n, 21, scale=1.0)
+    A *= norm / np.abs(A).sum(0).max()
+    got = setd.phi_matrices(dev(A), 1.0, 4).cpu().numpy()
+    ref = oracle.phi_all(A, 4)
+    for k in range(5):
+        G = got[k].reshape(n, n, order="F")
+        assert rel_err(G, ref[k]) < 1e-13, (n, norm, k, rel_err(G, ref[k]))
 
 
 def test_phi_rejects_nonfinite():
