@@ -8,7 +8,9 @@ step are written here a second time, from the paper, in plain numpy.
 
 Contents
   coeffs  - Table 1 (real, d = 2) and Table 3 (d > 2) closed forms, "+" set
-  phi     - phi_0..phi_p of small matrices via the augmented-matrix exponential
+  phi     - phi_0..phi_p of small matrices: exact spectral form (long double)
+            for multiples of the Neumann pattern, augmented-matrix exponential
+            otherwise
   tensor  - mu-mode product, Tucker operator, Kronecker-sum action (Section 2)
   etd     - reaction terms, phi bank, split phi action, eq. (exprk3) step
   norms   - relative L2 / inf errors
