@@ -2,10 +2,10 @@
 the oracle, on the benchmark workloads and on ragged grids.
 
 Tolerance: 1e-12 relative L2 per field (and relative inf), the FP64 bar.  The
-two sides differ only in rounding order and in the phi matrices, which both
-carry an error of about u * ||tau alpha A|| (the phi of a stiff matrix is
-only determined that well by the matrix); that error enters each step
-multiplied by tau and by the small update, far below 1e-12 of the field.
+two sides evaluate the phi matrices to within a few ulps (the oracle through
+the exact eigen-decomposition of the Neumann matrices, the library in
+double-double), so they differ only in the rounding order of the mode
+products, stage sums and reaction.
 """
 import numpy as np
 import pytest
@@ -80,17 +80,18 @@ def test_fhn_128_steps():
     _assert_close(_run_gpu(prob, 6), _run_oracle(prob, 6))
 
 
-@pytest.mark.parametrize("dims", [(16, 8, 192), (64, 192, 3), (192, 64, 4)])
-def test_lds_panel_paths(dims):
+@pytest.mark.parametrize("dims,nsteps", [((16, 8, 192), 2), ((64, 192, 3), 2), ((192, 64, 4), 2),
+                                          ((16, 8, 256), 3), ((256, 8, 4), 3)])
+def test_lds_panel_paths(dims, nsteps):
     """Grids whose mode products take the LDS-panel kernels: a last mode of
     192 (three-term jobs, the panel refilled per term), a middle mode of 192
     with 64 rows per slab (single-term jobs, several tiles per wave), a first
-    mode of 192.  (A 256-point last mode on a thin grid sits at 1.7e-12 after
-    three steps with every kernel: the phi matrices of that stiff direction
-    carry about u times their norm.)"""
+    mode of 192; and a 256-point last or first mode on a thin grid, the
+    stiffest direction of the benchmark (its phi matrices have ||X||_1 up to
+    1.8e5)."""
     prob = wl.fhn_3d(dims=dims)
-    say("lds panel paths", dims)
-    _assert_close(_run_gpu(prob, 2), _run_oracle(prob, 2))
+    say("lds panel paths", dims, nsteps)
+    _assert_close(_run_gpu(prob, nsteps), _run_oracle(prob, nsteps))
 
 
 @pytest.mark.parametrize("case", ["fhn_ragged", "schnak_ragged", "fhn_nonsquare", "schnak_rect"])

@@ -143,9 +143,18 @@ def test_sampled_tucker_full_size():
 
 
 def _phi_tol(X):
-    # phi of a stiff matrix is determined to ~u ||X|| by X itself (see the
-    # oracle's spectral pin); both sides carry such an error.
+    # against the oracle's augmented-matrix exponential (general matrices):
+    # that FP64 evaluation carries an error of about u ||X|| itself
     return 1e-13 + 4.4e-16 * np.abs(X).sum(0).max()
+
+
+# Multiples of the Neumann second difference: the oracle evaluates them
+# through the exact eigen-decomposition in long double (within an ulp of the
+# 40-digit value, pinned on the CPU), and the library rounds a double-double
+# Pade / squaring result once, so the two agree to a few FP64 ulps of the
+# largest entry whatever ||X|| is.  An FP64 squaring method would be off by
+# about u ||X|| (2e-11 at the stiffest 256-point matrix below).
+PHI_NEUMANN_TOL = 1e-15
 
 
 @pytest.mark.parametrize("n,c", [(1, 0.3), (5, 0.0), (9, 1e-3), (33, 0.05), (64, 2.0), (128, 0.5), (256, 0.67),
@@ -157,7 +166,38 @@ def test_phi_matrices_neumann(n, c):
     ref = oracle.phi_all(c * A, 2)
     for k in range(3):
         G = got[k].reshape(n, n, order="F")
-        assert rel_err(G, ref[k]) < _phi_tol(c * A), (n, c, k, rel_err(G, ref[k]))
+        say("  order", k, "err %.3e" % rel_err(G, ref[k]))
+        assert rel_err(G, ref[k]) < PHI_NEUMANN_TOL, (n, c, k, rel_err(G, ref[k]))
+
+
+def _bank_scalars(tau, d=3):
+    """Every scalar c_s tau alpha_{i,mu} of the phi bank of Algorithm 2
+    (Algorithm 1 for d = 2), and tau itself (second-order splitting)."""
+    from oracle import etd as oetd
+    from oracle.coeffs import split_coefficients
+    out = {tau}
+    for s, ell in oetd.BANK_ENTRIES:
+        _, _, alpha = split_coefficients(ell, d)
+        for z in np.ravel(oetd.STAGE_SCALE[s] * tau * alpha):
+            out.add(float(z))
+    return sorted(out)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("diff", [1.0, 42.1])
+def test_phi_bank_scalars_stiff(n, diff):
+    """phi_0..phi_2 at every bank scalar of the 3D FitzHugh-Nagumo workloads
+    (tau = 1e-2, d_u = 1, d_v = 42.1; ||X||_1 up to 1.8e5 at n = 256)."""
+    A = diff * neumann_d2(n)
+    worst = 0.0
+    for z in _bank_scalars(1e-2):
+        got = setd.phi_matrices(dev(A), z, 2).cpu().numpy()
+        ref = oracle.phi_all(z * A, 2)
+        for k in range(3):
+            e = rel_err(got[k].reshape(n, n, order="F"), ref[k])
+            worst = max(worst, e)
+            assert e < PHI_NEUMANN_TOL, (n, diff, z, k, e)
+    say("phi bank scalars", n, diff, "worst %.3e" % worst)
 
 
 @pytest.mark.parametrize("n,scale", [(7, 0.5), (40, 3.0), (100, 0.01)])
