@@ -121,6 +121,25 @@ size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec);
 int setd_release_workspace(void);
 
 /*
+ * setd_tucker_apply without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * setd_tucker_apply, but the Tucker intermediates and packed matrices live in
+ * a scratch array of SETD_NOALLOC_SCRATCH_BYTES (64 MiB) that the library
+ * holds on each GPU until the process ends; a tensor whose
+ * setd_tucker_workspace_bytes exceeds it (e.g. beyond 128^3 in FP64, whose
+ * need is 34 MB) is rejected with SETD_EINVAL before anything runs.  The
+ * call allocates nothing and does not synchronise `stream`.
+ * Every call on one GPU uses that GPU's single array: calls that overlap in
+ * time on one GPU (different streams or threads) race and must be serialised
+ * by the caller.  Nothing in the array needs to be cleared between calls.
+ */
+#define SETD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int setd_tucker_apply_noalloc(const double* V, double* W, int d, const int64_t* dims,
+                              const double* const* M, double alpha, double beta, int prec,
+                              void* stream);
+
+/*
  * Integration context: one grid, one set of matrices A_mu^(c) per component,
  * one step size tau and one arithmetic.  Creating it builds the phi bank
  * P_{i,s}^(l){mu} = phi_{l_i}(c_s tau alpha_{i,mu}^(l) A_mu) of Algorithm 1

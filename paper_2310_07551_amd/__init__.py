@@ -17,7 +17,7 @@ from ._lib import (G_FHN, G_NONE, G_SCHNAKENBERG, PREC_BF16X2, PREC_BF16X3, PREC
                    STAGE_F, SetdError)
 
 __all__ = [
-    "phi_matrices", "tucker_apply", "Context", "Batch", "field_norms", "profile_enable", "profile_read", "colmajor", "version", "SetdError",
+    "phi_matrices", "tucker_apply", "tucker_apply_noalloc", "Context", "Batch", "field_norms", "profile_enable", "profile_read", "colmajor", "version", "SetdError",
     "G_NONE", "G_SCHNAKENBERG", "G_FHN", "PREC_F64", "PREC_F32", "PREC_BF16X3", "PREC_BF16X2", "STAGE_2", "STAGE_3",
     "STAGE_F",
 ]
@@ -91,6 +91,26 @@ def tucker_apply(V, W, dims: Sequence[int], mats: Sequence[Optional[object]], al
     lib = _lib.load()
     _lib.check(lib.setd_tucker_apply(V.data_ptr(), W.data_ptr(), d, cdims, ptrs, float(alpha), float(beta),
                                      int(prec), ws_ptr, ws_bytes, _stream(stream)))
+    return W
+
+
+def tucker_apply_noalloc(V, W, dims: Sequence[int], mats: Sequence[Optional[object]], alpha: float = 1.0,
+                         beta: float = 0.0, prec: int = PREC_F64, stream=None):
+    """tucker_apply through setd_tucker_apply_noalloc: no device allocation,
+    the library's per-GPU scratch array (NOALLOC_SCRATCH_BYTES) as workspace."""
+    _check_dev(V, "V")
+    _check_dev(W, "W")
+    d = len(dims)
+    cdims = (ctypes.c_int64 * d)(*[int(x) for x in dims])
+    ptrs = (ctypes.c_void_p * d)()
+    for mu, M in enumerate(mats):
+        if M is None:
+            ptrs[mu] = None
+        else:
+            _check_dev(M, "M[%d]" % mu)
+            ptrs[mu] = M.data_ptr()
+    _lib.check(_lib.load().setd_tucker_apply_noalloc(V.data_ptr(), W.data_ptr(), d, cdims, ptrs, float(alpha),
+                                                     float(beta), int(prec), _stream(stream)))
     return W
 
 

@@ -38,6 +38,8 @@ SIGNATURES = {
     "setd_tucker_apply": (_c_int, [_vp, _vp, _c_int, ctypes.POINTER(_c_i64), ctypes.POINTER(_vp), _c_double,
                                    _c_double, _c_int, _vp, _c_size, _vp]),
     "setd_tucker_workspace_bytes": (_c_size, [_c_int, ctypes.POINTER(_c_i64), _c_int]),
+    "setd_tucker_apply_noalloc": (_c_int, [_vp, _vp, _c_int, ctypes.POINTER(_c_i64), ctypes.POINTER(_vp),
+                                           _c_double, _c_double, _c_int, _vp]),
     "setd_release_workspace": (_c_int, []),
     "setd_ctx_create": (_c_int, [ctypes.POINTER(_vp), _c_int, ctypes.POINTER(_c_i64), _c_int, ctypes.POINTER(_vp),
                                  _c_double, _c_int, _vp]),
@@ -68,6 +70,7 @@ SIGNATURES = {
 }
 
 BATCH_INFO = 10
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SETD_NOALLOC_SCRATCH_BYTES
 
 PROF_CLASSES = ("mode1_f64", "modeB_f64", "mode1_lp", "modeB_lp", "pointwise", "modeB_panel_f64")
 

@@ -560,6 +560,35 @@ int run_steps(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const 
 
 }  // namespace
 
+// Scratch memory of setd_tucker_apply_noalloc: the Tucker intermediates and
+// packed matrices of one call.  Each GPU the library runs on holds its own
+// copy until the process ends.  In host code this name is only a stand-in
+// for the device array: kernels and copies get the address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[SETD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  SETD_HIP(hipGetDevice(&dev));
+  SETD_CHECK_ARG(dev >= 0 && dev < kMaxScratchDevices, "device %d outside 0..%d", dev, kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    SETD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    SETD_CHECK_ARG(p != nullptr, "no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SETD_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* setd_last_error(void) { return g_err; }
@@ -629,6 +658,20 @@ int setd_phi_matrices(const double* A, int64_t n, double tau, int ell, double* o
   std::vector<double*> outs(ell + 1);
   for (int k = 0; k <= ell; ++k) outs[k] = out + (size_t)k * n * n;
   return phi_batch(A, (int)n, &tau, 1, ell, outs.data(), s);
+}
+
+int setd_tucker_apply_noalloc(const double* V, double* W, int d, const int64_t* dims, const double* const* M,
+                              double alpha, double beta, int prec, void* stream) {
+  clear_error();
+  // need is 0 for arguments setd_tucker_apply rejects; it reports them below
+  // (with a workspace given it never allocates)
+  const size_t need = setd_tucker_workspace_bytes(d, dims, prec);
+  SETD_CHECK_ARG(need <= (size_t)SETD_NOALLOC_SCRATCH_BYTES,
+                 "tensor needs %zu bytes of scratch, more than the %zu bytes setd_tucker_apply_noalloc holds", need,
+                 (size_t)SETD_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  SETD_TRY(noalloc_scratch(&ws));
+  return setd_tucker_apply(V, W, d, dims, M, alpha, beta, prec, ws, (size_t)SETD_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec) {
