@@ -7,12 +7,24 @@ is quoted on.  W warm-up steps, then exactly K timed steps between two device
 synchronisations; the phi bank is built before (its time is reported apart,
 as the paper does).  Prints one JSON line on stdout.
 
-Roofline: while the K steps run, every library kernel launch is bracketed by
-HIP events on the launch stream (setd_profile_*); the dominant kernel class
-(by total time) is reported with its algorithmic flops (2 N n per mode
-product term) divided by its measured time, against the MI355X FP64 matrix
-peak.  cpu_baseline: the FP64 oracle timed on this host for a bounded sample
-of the same workload (one step by default, phi bank excluded).
+The K timed steps run as the library runs them by default: each step a
+replay of its captured hipGraph, no per-launch events.  The same K steps are
+then run a second time with every library kernel launch bracketed by HIP
+events on its launch stream (setd_profile_*; per-launch events and graph
+replay exclude each other): the per-class kernel table and the roofline come
+from that pass.  The dominant kernel class (by total time) is reported with
+its algorithmic flops (2 N n per mode product term) divided by its measured
+time, against the MI355X FP64 matrix peak; each reduced-precision form gets
+the same against the peak of its own arithmetic.
+
+Accuracy: for the 3D FitzHugh-Nagumo workloads each form also runs a clean
+trajectory of the stored step counts from u0 and is compared with the FP64
+oracle's stored values (tests/golden, sampled points and whole-field norms)
+and, field by field, with the library's FP64 trajectory.
+
+cpu_baseline: the FP64 oracle timed on this host for a bounded sample of the
+same workload (one step by default, phi bank excluded), with the host CPU
+model and core counts.
 """
 from __future__ import annotations
 
@@ -27,8 +39,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "split-ETD3 steps/s + Tucker TFLOP/s (%MFMA peak), 3D FHN 256³, FP64 vs split"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
+# matrix-core products per algorithmic product (three-piece split: 6, two-piece: 3)
+MFMA_PER_PRODUCT = {"f64": 1, "f32": 1, "bf16x3": 6, "bf16x2": 3}
 PEAK_HBM_GBS = 8000.0
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 
 
 def log(*a):
@@ -137,6 +152,69 @@ def library_gemm(n=256, reps=20):
     print(json.dumps(out), flush=True)
 
 
+def host_cpu():
+    """(model name, physical cores, logical CPUs) of this host from /proc/cpuinfo."""
+    model, phys = "unknown", set()
+    try:
+        cur = {}
+        with open("/proc/cpuinfo") as fh:
+            for line in fh.read().splitlines() + [""]:
+                if not line.strip():
+                    if "core id" in cur:
+                        phys.add((cur.get("physical id", "0"), cur["core id"]))
+                    cur = {}
+                    continue
+                k, _, v = line.partition(":")
+                cur[k.strip()] = v.strip()
+                if k.strip() == "model name":
+                    model = v.strip()
+    except OSError:
+        pass
+    logical = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = logical
+    return model, (len(phys) or None), logical, avail
+
+
+def read_golden(n, step):
+    """Stored FP64 oracle values of fhn3d_<n> at `step` (tests/golden, written
+    by tests/golden/make_fhn3d_goldens.py): (norms, sample indices, values)."""
+    import numpy as np
+    path = os.path.join(GOLDEN_DIR, "fhn3d_%d_step%04d.txt" % (n, step))
+    if not os.path.exists(path):
+        return None
+    norms, rows = {}, []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        f = line.split()
+        if f[0] == "norm":
+            norms[(f[1], f[2])] = float(f[3])
+        elif f[0] not in ("step", "samples"):
+            rows.append((int(f[0]), float(f[1]), float(f[2])))
+    idx = np.asarray([r[0] for r in rows], dtype=np.int64)
+    vals = np.asarray([(r[1], r[2]) for r in rows])
+    return norms, idx, vals
+
+
+def golden_errors(u, N, golden):
+    """Per field: relative L2 and max error over the stored sample points, and
+    the relative error of the whole-field L2 norm, against the oracle."""
+    import numpy as np
+    norms, idx, vals = golden
+    x = u.detach().cpu().numpy()
+    out = {}
+    for c, name in enumerate(("u", "v")):
+        f = x[c * N:(c + 1) * N]
+        got, ref = f[idx], vals[:, c]
+        out[name] = dict(samples_rel_l2=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                         samples_rel_inf=float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
+                         norm_l2_rel=float(abs(np.linalg.norm(f) - norms[(name, "l2")]) / norms[(name, "l2")]))
+    return out
+
+
 def cpu_baseline(prob, nsteps):
     import numpy as np
     import oracle
@@ -145,6 +223,7 @@ def cpu_baseline(prob, nsteps):
         threads = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
+    model, phys, logical, avail = host_cpu()
     banks = oracle.make_banks(prob.A, prob.tau)
     U = [np.array(x) for x in prob.U0]
     t0 = time.perf_counter()
@@ -153,7 +232,9 @@ def cpu_baseline(prob, nsteps):
     dt = time.perf_counter() - t0
     return dict(value=nsteps / dt, unit="steps/s", cores=threads, kind="oracle",
                 sample="%d step(s) of %s %s (numpy FP64, phi bank excluded), %.1f s" %
-                (nsteps, prob.name, "x".join(map(str, prob.dims)), dt))
+                (nsteps, prob.name, "x".join(map(str, prob.dims)), dt),
+                cpu_model=model, physical_cores=phys, logical_cpus=logical, cpus_available=avail,
+                threads_note="cores = BLAS threads the oracle's products ran on")
 
 
 def run_batch(torch, setd, wl, warmup=3, serial_steps=10):
@@ -326,8 +407,10 @@ def main():
     u0 = torch.from_numpy(prob.u0_flat()).to(dev)
 
     def run_form(prec, steps, warmup):
-        """phi bank, W warm-up steps, K timed steps (events on); returns
-        (phi seconds, timed seconds, per-class profile, final state)."""
+        """phi bank, W warm-up steps, K timed steps (graph replay, no events),
+        then K more steps with per-launch events.  Returns the open context,
+        phi seconds, timed seconds, profiled seconds, per-class profile and
+        the state after the timed steps."""
         u = u0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -336,38 +419,101 @@ def main():
         phi = time.perf_counter() - t0
         ctx.step(u, warmup, prob.g_kind, prob.params)
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(u, steps, prob.g_kind, prob.params)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        u_timed = u.clone()
         setd.profile_enable(True)
         setd.profile_read(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.step(u, steps, prob.g_kind, prob.params)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dtp = time.perf_counter() - t0
         prof = setd.profile_read(reset=True)
         setd.profile_enable(False)
-        ctx.close()
-        return phi, dt, prof, u
+        return ctx, phi, dt, dtp, prof, u_timed
 
-    phi_s, dt, prof, u = run_form(setd.PREC_F64, args.steps, args.warmup)
-    log("phi bank %.3f s, %d steps in %.3f s" % (phi_s, args.steps, dt))
+    # stored oracle values of this workload (3D FitzHugh-Nagumo grids)
+    goldens = {}
+    if prob.name == "fhn3d" and len(set(prob.dims)) == 1:
+        for k in range(1, prob.nsteps + 1):
+            g = read_golden(prob.dims[0], k)
+            if g is not None:
+                goldens[k] = g
+
+    def accuracy(ctx, ref_states=None):
+        """A clean trajectory from u0 to each stored step count: errors against
+        the oracle's stored values and, when given, the FP64 states."""
+        u = u0.clone()
+        done, res, states = 0, {}, {}
+        for k in sorted(goldens):
+            ctx.step(u, k - done, prob.g_kind, prob.params)
+            torch.cuda.synchronize()
+            done = k
+            res[k] = golden_errors(u, prob.N, goldens[k])
+            states[k] = u.clone()
+            if ref_states is not None:
+                for c, name in enumerate(("u", "v")):
+                    e = setd.field_norms(u[c * prob.N:(c + 1) * prob.N], ref_states[k][c * prob.N:(c + 1) * prob.N])
+                    res[k][name]["rel_l2_vs_f64"] = e[2] / e[0]
+        return res, states
+
+    def form_roofline(prof_l, name):
+        """Dominant reduced-precision mode class against the peak of its own
+        arithmetic (matrix-core flops = algorithmic flops x products per
+        product) or HBM, whichever bounds it."""
+        cls = max(("mode1_lp", "modeB_lp"), key=lambda k: prof_l[k]["ms"])
+        v = prof_l[cls]
+        if v["ms"] <= 0:
+            return None
+        sec = v["ms"] * 1e-3
+        mfma = v["flops"] * MFMA_PER_PRODUCT[name]
+        t_compute = mfma / (PEAK_TFLOPS[name] * 1e12)
+        t_memory = v["bytes"] / (PEAK_HBM_GBS * 1e9)
+        if t_compute >= t_memory:
+            ach = mfma / sec / 1e12
+            r = dict(bound="mfma", achieved=round(ach, 3), peak=PEAK_TFLOPS[name], unit="TFLOP/s",
+                     frac=round(ach / PEAK_TFLOPS[name], 4))
+        else:
+            ach = v["bytes"] / sec / 1e9
+            r = dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                     frac=round(ach / PEAK_HBM_GBS, 4))
+        r.update(kernel=cls, launches=v["launches"], avg_launch_ms=round(v["ms"] / max(1, v["launches"]), 4),
+                 algorithmic_tflops=round(v["flops"] / sec / 1e12, 3), algorithmic_gbs=round(v["bytes"] / sec / 1e9, 1),
+                 traffic=None)
+        return r
+
+    ctx, phi_s, dt, dtp, prof, u = run_form(setd.PREC_F64, args.steps, args.warmup)
+    log("phi bank %.3f s, %d steps in %.3f s (graph replay), %.3f s with per-launch events" %
+        (phi_s, args.steps, dt, dtp))
     norms = setd.field_norms(u[:prob.N])
     if not all(map(lambda x: x == x and abs(x) != float("inf"), norms)):
         log("non-finite state after the timed steps")
         sys.exit(1)
+    acc64, states64 = accuracy(ctx) if goldens else ({}, {})
+    ctx.close()
+    for k, e in acc64.items():
+        log("f64 vs stored oracle at step %d: %s" % (k, {f: "%.2e" % v["samples_rel_l2"] for f, v in e.items()}))
 
     forms = {}
     for name in [f for f in args.forms.split(",") if f in ("f32", "bf16x3", "bf16x2")]:
         prec = {"f32": setd.PREC_F32, "bf16x3": setd.PREC_BF16X3, "bf16x2": setd.PREC_BF16X2}[name]
-        phi_l, dt_l, prof_l, u_l = run_form(prec, args.steps, args.warmup)
-        errs = [setd.field_norms(u_l[c * prob.N:(c + 1) * prob.N], u[c * prob.N:(c + 1) * prob.N]) for c in range(2)]
+        ctx_l, phi_l, dt_l, dtp_l, prof_l, u_l = run_form(prec, args.steps, args.warmup)
+        acc_l, _ = accuracy(ctx_l, states64) if goldens else ({}, {})
+        ctx_l.close()
         ms = sum(prof_l[k]["ms"] for k in ("mode1_lp", "modeB_lp"))
         fl = sum(prof_l[k]["flops"] for k in ("mode1_lp", "modeB_lp"))
+        last = max(acc_l) if acc_l else None
+        worst = max(v["rel_l2_vs_f64"] for v in acc_l[last].values()) if last else None
         forms[name] = dict(steps_per_s=round(args.steps / dt_l, 4), ms_per_step=round(dt_l / args.steps * 1e3, 4),
                            speedup_vs_f64=round(dt / dt_l, 3),
-                           rel_l2_vs_f64=[e[2] / e[0] for e in errs],
+                           accuracy=acc_l, accuracy_step=last, worst_rel_l2_vs_f64=worst,
+                           meets_1e_5=(worst is not None and worst <= 1e-5),
                            tucker_tflops=round(fl / (ms * 1e-3) / 1e12, 3) if ms > 0 else None,
-                           phi_setup_s=round(phi_l, 3))
-        log("%s: %.2f steps/s, rel_l2 vs f64 %s" % (name, args.steps / dt_l, forms[name]["rel_l2_vs_f64"]))
+                           roofline=form_roofline(prof_l, name), phi_setup_s=round(phi_l, 3))
+        log("%s: %.2f steps/s, worst rel_l2 vs f64 at step %s: %s" % (name, args.steps / dt_l, last, worst))
 
     batch = run_batch(torch, setd, wl) if "batch" in args.forms.split(",") else None
     methods = run_methods(torch, setd, prob, A, u0, dt / args.steps) if "methods" in args.forms.split(",") else None
@@ -415,6 +561,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(prob.dims), "tau": prob.tau, "components": 2,
                    "kinetics": prob.name, "phi_setup_s": round(phi_s, 3)},
+        "timing": "graph replay, no per-launch events; kernels and roofline from a second pass of the same "
+                  "steps with per-launch events",
+        "profiled_ms_per_step": round(dtp / args.steps * 1e3, 4),
+        "f64_vs_oracle": acc64,
         "tucker_tflops": round(tucker_tflops, 3),
         "tucker_frac_peak": round(tucker_tflops / PEAK_TFLOPS["f64"], 4),
         "tucker_flops_per_step": flops_step,

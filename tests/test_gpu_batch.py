@@ -150,3 +150,44 @@ def test_batch_64_instances_full_size_sampled():
     sizes = [p.N for p in probs]
     order = np.argsort(sizes, kind="stable")
     _check(B, u, probs, steps, which=[int(order[0]), int(order[len(order) // 2]), int(order[-1])])
+
+
+def _batch_golden(step):
+    import importlib.util
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_batch_goldens", os.path.join(here, "make_batch_goldens.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    path = os.path.join(here, "batch64_step%04d.txt" % step)
+    assert os.path.exists(path), path
+    return mod.read_golden(path)[1]
+
+
+def test_batch_64_instances_all_against_stored_oracle():
+    """All 64 instances of the batching workload (tuned tiles, graph replay)
+    through its 100 steps, against the oracle's stored values of every
+    instance at steps 20 and 100 (sampled points and whole-field L2 norms)."""
+    probs = wl.schnakenberg_batch()
+    B = _make(probs)
+    say("tuned", B.tune())
+    u = _state(B, probs)
+    params = [p.params for p in probs]
+    done, worst = 0, 0.0
+    for step in (20, 100):
+        gold = _batch_golden(step)
+        B.step(u, step - done, probs[0].g_kind, params)
+        torch().cuda.synchronize()
+        done = step
+        assert torch().isfinite(u).all()
+        for b, p in enumerate(probs):
+            dims, norms, idx, vals = gold[b]
+            assert tuple(dims) == tuple(p.dims)
+            for c in range(2):
+                f = B.field(u, b, c).cpu().numpy()
+                got, ref = f[idx], vals[:, c]
+                e2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+                ei = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+                en = abs(np.linalg.norm(f) - norms[c]) / norms[c]
+                worst = max(worst, e2, ei, en)
+                assert e2 < TOL and ei < TOL and en < TOL, (step, b, p.dims, c, e2, ei, en)
+        say("  step %d: all 64 instances within %.3e" % (step, worst))
