@@ -13,7 +13,6 @@ Contents
             otherwise
   tensor  - mu-mode product, Tucker operator, Kronecker-sum action (Section 2)
   etd     - reaction terms, phi bank, split phi action, eq. (exprk3) step
-  norms   - relative L2 / inf errors
   adjoint - discrete adjoint of the step (vector-Jacobian product), loss
             gradients with respect to U0, reaction parameters and diffusion
             scale (import as oracle.adjoint)
@@ -25,7 +24,6 @@ special cases, observed convergence orders); see those tests for the list.
 from .coeffs import split_coefficients, table1_real, table3_real
 from .etd import (BANK_ENTRIES, G_FHN, G_NONE, G_SCHNAKENBERG, STAGE_SCALE, PhiBank, etd_step, integrate,
                   make_banks, reaction, split2_apply, Phi2Bank, etd2rkds_step, integrate_etd2rkds)
-from .norms import rel_inf, rel_l2
 from .phi import phi, phi_all
 from .tensor import kron_sum_action, mode_product, tucker
 
@@ -33,5 +31,5 @@ __all__ = [
     "split_coefficients", "table1_real", "table3_real", "BANK_ENTRIES", "G_FHN", "G_NONE", "G_SCHNAKENBERG",
     "STAGE_SCALE", "PhiBank", "etd_step", "integrate", "make_banks", "reaction", "split2_apply",
     "Phi2Bank", "etd2rkds_step", "integrate_etd2rkds",
-    "rel_inf", "rel_l2", "phi", "phi_all", "kron_sum_action", "mode_product", "tucker",
+    "phi", "phi_all", "kron_sum_action", "mode_product", "tucker",
 ]
