@@ -370,61 +370,89 @@ int launch_stage_d(const double* Us, const double* G, int ncomp, int64_t N, cons
 // ---------------------------------------------------------------------------
 // deterministic norms
 // ---------------------------------------------------------------------------
-constexpr int kNormBlocks = 512;
+// Pass 1: block b reduces a contiguous chunk of x (and x - y): each thread
+// strides through it, the 64 lanes of a wave combine by an xor-shuffle
+// butterfly, the block's four waves in LDS in wave order.  Pass 2: one block
+// reduces the per-block partials the same way.  Every addition happens in an
+// order fixed by the launch shape, so repeated calls give identical bits.
+constexpr int kNormBlocks = 1024;
 constexpr int kNormThreads = 256;
 
 __device__ __forceinline__ double nanmax(double a, double b) {
   return (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
 }
 
-__global__ void norm_pass1(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
-                           double* __restrict__ part) {
-  __shared__ double s[4][kNormThreads];
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nanmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Combines the four per-thread values {sum, max, sum, max} of a 256-thread
+// block; thread 0 returns the block's result in r.
+__device__ __forceinline__ void block_reduce4(double (&r)[4]) {
+  __shared__ double w[4][kNormThreads / 64];
+  r[0] = wave_sum(r[0]);
+  r[1] = wave_max(r[1]);
+  r[2] = wave_sum(r[2]);
+  r[3] = wave_max(r[3]);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; ++k) w[k][wave] = r[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) r[k] = w[k][0];
+    for (int v = 1; v < kNormThreads / 64; ++v) {
+      r[0] += w[0][v];
+      r[1] = nanmax(r[1], w[1][v]);
+      r[2] += w[2][v];
+      r[3] = nanmax(r[3], w[3][v]);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kNormThreads) norm_pass1(const double* __restrict__ x, const double* __restrict__ y,
+                                                            int64_t n, double* __restrict__ part) {
   const int64_t chunk = ceil_div_dev(n, (int64_t)gridDim.x);
   const int64_t beg = chunk * blockIdx.x;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
-  double ss = 0.0, mx = 0.0, dss = 0.0, dmx = 0.0;
-  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = beg + threadIdx.x; i < end; i += kNormThreads) {
     const double v = x[i];
-    ss += v * v;
-    mx = nanmax(mx, fabs(v));
+    r[0] = fma(v, v, r[0]);
+    r[1] = nanmax(r[1], fabs(v));
     if (y) {
       const double e = v - y[i];
-      dss += e * e;
-      dmx = nanmax(dmx, fabs(e));
+      r[2] = fma(e, e, r[2]);
+      r[3] = nanmax(r[3], fabs(e));
     }
   }
-  s[0][threadIdx.x] = ss;
-  s[1][threadIdx.x] = mx;
-  s[2][threadIdx.x] = dss;
-  s[3][threadIdx.x] = dmx;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s[0][threadIdx.x] += s[0][threadIdx.x + w];
-      s[1][threadIdx.x] = nanmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
-      s[2][threadIdx.x] += s[2][threadIdx.x + w];
-      s[3][threadIdx.x] = nanmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
+  block_reduce4(r);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = s[k][0];
+    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = r[k];
 }
 
-__global__ void norm_pass2(const double* __restrict__ part, int nblk, double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
-  double ss = 0, mx = 0, dss = 0, dmx = 0;
-  for (int b = 0; b < nblk; ++b) {
-    ss += part[4 * b];
-    mx = nanmax(mx, part[4 * b + 1]);
-    dss += part[4 * b + 2];
-    dmx = nanmax(dmx, part[4 * b + 3]);
+__global__ void __launch_bounds__(kNormThreads) norm_pass2(const double* __restrict__ part, double* __restrict__ out) {
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < kNormBlocks; b += kNormThreads) {
+    r[0] += part[4 * b];
+    r[1] = nanmax(r[1], part[4 * b + 1]);
+    r[2] += part[4 * b + 2];
+    r[3] = nanmax(r[3], part[4 * b + 3]);
   }
-  out[0] = sqrt(ss);
-  out[1] = mx;
-  out[2] = sqrt(dss);
-  out[3] = dmx;
+  block_reduce4(r);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(r[0]);
+    out[1] = r[1];
+    out[2] = sqrt(r[2]);
+    out[3] = r[3];
+  }
 }
 
 size_t norm_workspace_bytes() { return (size_t)(4 * kNormBlocks + 4) * sizeof(double); }
@@ -432,7 +460,7 @@ size_t norm_workspace_bytes() { return (size_t)(4 * kNormBlocks + 4) * sizeof(do
 int launch_norms(const double* x, const double* y, int64_t n, double* ws, hipStream_t s) {
   hipLaunchKernelGGL(norm_pass1, dim3(kNormBlocks), dim3(kNormThreads), 0, s, x, y, n, ws);
   SETD_LAUNCHED();
-  hipLaunchKernelGGL(norm_pass2, dim3(1), dim3(64), 0, s, ws, kNormBlocks, ws + 4 * kNormBlocks);
+  hipLaunchKernelGGL(norm_pass2, dim3(1), dim3(kNormThreads), 0, s, ws, ws + 4 * kNormBlocks);
   SETD_LAUNCHED();
   return SETD_OK;
 }
