@@ -39,9 +39,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "split-ETD3 steps/s + Tucker TFLOP/s (%MFMA peak), 3D FHN 256³, FP64 vs split"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
-# matrix-core products per algorithmic product (three-piece split: 6, two-piece: 3)
-MFMA_PER_PRODUCT = {"f64": 1, "f32": 1, "bf16x3": 6, "bf16x2": 3}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0, "i8x4": 5000.0}
+# matrix-core products per algorithmic product (three-piece split: 6, two-piece: 3,
+# int8 digit slicing: the thirteen digit pairs of order >= 2)
+MFMA_PER_PRODUCT = {"f64": 1, "f32": 1, "bf16x3": 6, "bf16x2": 3, "i8x4": 13}
 PEAK_HBM_GBS = 8000.0
 GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 
@@ -375,8 +376,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of this size (HBM counter calibration) and exit")
-    ap.add_argument("--forms", default="f64,f32,bf16x3,bf16x2,batch,methods,adjoint",
-                    help="forms to time besides the FP64 metric: f32, bf16x3, bf16x2 (compared against f64), "
+    ap.add_argument("--forms", default="f64,i8x4,f32,bf16x3,bf16x2,batch,methods,adjoint",
+                    help="forms to time besides the FP64 metric: i8x4, f32, bf16x3, bf16x2 (compared against f64), "
                          "batch (64 uneven 2D Schnakenberg instances, 100 steps), methods (exprk3ds_cplx and "
                          "etd2rkds on the same workload) and adjoint (gradient of the 3D FHN 128^3, 200-step loss)")
     ap.add_argument("--library-gemm", action="store_true",
@@ -498,8 +499,9 @@ def main():
         log("f64 vs stored oracle at step %d: %s" % (k, {f: "%.2e" % v["samples_rel_l2"] for f, v in e.items()}))
 
     forms = {}
-    for name in [f for f in args.forms.split(",") if f in ("f32", "bf16x3", "bf16x2")]:
-        prec = {"f32": setd.PREC_F32, "bf16x3": setd.PREC_BF16X3, "bf16x2": setd.PREC_BF16X2}[name]
+    for name in [f for f in args.forms.split(",") if f in ("i8x4", "f32", "bf16x3", "bf16x2")]:
+        prec = {"f32": setd.PREC_F32, "bf16x3": setd.PREC_BF16X3, "bf16x2": setd.PREC_BF16X2,
+                "i8x4": setd.PREC_I8X4}[name]
         ctx_l, phi_l, dt_l, dtp_l, prof_l, u_l = run_form(prec, args.steps, args.warmup)
         acc_l, _ = accuracy(ctx_l, states64) if goldens else ({}, {})
         ctx_l.close()

@@ -57,6 +57,14 @@ extern "C" {
                                   with FP32 accumulate; FP32 intermediates     */
 #define SETD_PREC_BF16X2  3    /* two-term split x = h + l; h*h, h*l, l*h (three
                                   products): faster, about 16 significant bits */
+#define SETD_PREC_I8X4    4    /* error-free int8 slicing (Ozaki scheme): every
+                                  phi row and tensor fibre as 30-bit integers
+                                  relative to its largest entry, four int8
+                                  digits each; the ten digit products of order
+                                  >= 3 summed exactly in int32 on the int8
+                                  matrix cores, combined in FP64 (about 2^-29
+                                  of |x|max |p|max per product term); FP64
+                                  inputs, intermediates and outputs          */
 
 /* ---- reaction terms g (eq. twocompdisc: two components u, v) ---- */
 #define SETD_G_NONE         0  /* g = 0; nparams = 0                            */
@@ -103,8 +111,8 @@ int setd_phi_matrices(const double* A, int64_t n, double tau, int ell, double* o
  *   M      host array of d device pointers; M[mu] is the n_mu x n_mu
  *          column-major FP64 matrix applied along mode mu+1.  NULL means the
  *          identity (that mode is skipped).
- *   prec   SETD_PREC_F64, SETD_PREC_F32, SETD_PREC_BF16X3 or SETD_PREC_BF16X2
- *          (arithmetic of the mode products; V and W stay FP64).
+ *   prec   SETD_PREC_F64, SETD_PREC_F32, SETD_PREC_BF16X3, SETD_PREC_BF16X2 or
+ *          SETD_PREC_I8X4 (arithmetic of the mode products; V and W stay FP64).
  *   ws     device workspace of at least setd_tucker_workspace_bytes(d, dims,
  *          prec) bytes, or NULL to let the library use its own (grown on
  *          demand, kept until setd_release_workspace or process exit).

@@ -13,12 +13,12 @@ import ctypes
 from typing import Optional, Sequence
 
 from . import _lib
-from ._lib import (G_FHN, G_NONE, G_SCHNAKENBERG, PREC_BF16X2, PREC_BF16X3, PREC_F32, PREC_F64, STAGE_2, STAGE_3,
+from ._lib import (G_FHN, G_NONE, G_SCHNAKENBERG, PREC_BF16X2, PREC_BF16X3, PREC_F32, PREC_F64, PREC_I8X4, STAGE_2, STAGE_3,
                    STAGE_F, SetdError)
 
 __all__ = [
     "phi_matrices", "tucker_apply", "tucker_apply_noalloc", "Context", "Batch", "field_norms", "profile_enable", "profile_read", "colmajor", "version", "SetdError",
-    "G_NONE", "G_SCHNAKENBERG", "G_FHN", "PREC_F64", "PREC_F32", "PREC_BF16X3", "PREC_BF16X2", "STAGE_2", "STAGE_3",
+    "G_NONE", "G_SCHNAKENBERG", "G_FHN", "PREC_F64", "PREC_F32", "PREC_BF16X3", "PREC_BF16X2", "PREC_I8X4", "STAGE_2", "STAGE_3",
     "STAGE_F",
 ]
 

@@ -22,6 +22,7 @@ PREC_F64 = 0
 PREC_F32 = 1
 PREC_BF16X3 = 2
 PREC_BF16X2 = 3
+PREC_I8X4 = 4
 
 G_NONE = 0
 G_SCHNAKENBERG = 1

@@ -182,9 +182,20 @@ int pack_matrix_f64(const double* M, int n, double scale, bool rowmajor, double*
 int pack_matrix_f32(const double* M, int n, double scale, bool rowmajor, float* out, hipStream_t s);
 int pack_matrix_bf16(const double* M, int n, double scale, bool rowmajor, int np, void* out, hipStream_t s);
 inline bool is_prec(int p) {
-  return p == SETD_PREC_F64 || p == SETD_PREC_F32 || p == SETD_PREC_BF16X3 || p == SETD_PREC_BF16X2;
+  return p == SETD_PREC_F64 || p == SETD_PREC_F32 || p == SETD_PREC_BF16X3 || p == SETD_PREC_BF16X2 ||
+         p == SETD_PREC_I8X4;
+}
+// Arithmetics whose Tucker inputs and intermediates are stored in FP32 (the
+// others keep them in FP64).
+inline bool fp32_storage(int p) {
+  return p == SETD_PREC_F32 || p == SETD_PREC_BF16X3 || p == SETD_PREC_BF16X2;
 }
 size_t packed_bytes(int n, int prec);
+// Error-free int8 slicing (mode_i8.hip): packed matrix size, packing, and the
+// mode-product launcher (FP64 tensors, any regime).
+size_t packed_bytes_i8(int n);
+int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t s);
+int launch_mode_i8(ModeJobs& jobs, bool mode1, hipStream_t s);
 
 // Pointwise helpers (pointwise.hip).
 int launch_axpby(const double* x, double* y, int64_t n, double a, double b, hipStream_t s);  // y = a x + b y

@@ -63,6 +63,7 @@ size_t packed_bytes(int n, int prec) {
   if (prec == SETD_PREC_F64) return e * 8;
   if (prec == SETD_PREC_F32) return e * 4;
   if (prec == SETD_PREC_BF16X3) return e * 6;   // three bf16 planes
+  if (prec == SETD_PREC_I8X4) return packed_bytes_i8(n);
   return e * 4;                                 // two bf16 planes
 }
 

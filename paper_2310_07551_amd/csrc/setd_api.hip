@@ -112,6 +112,7 @@ struct LaunchKind {
 
 int launch_jobs(ModeJobs& J, const LaunchKind& k, hipStream_t s) {
   if (k.prec == SETD_PREC_F64) return k.mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
+  if (k.prec == SETD_PREC_I8X4) return launch_mode_i8(J, k.mode1, s);
   return k.mode1 ? launch_mode1_lp(J, k.prec, k.out, s) : launch_modeB_lp(J, k.prec, k.out, s);
 }
 
@@ -135,6 +136,7 @@ int push(ModeJobs& J, const ModeJob& jb, const LaunchKind& k, hipStream_t s) {
 int setd::pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s) {
   if (prec == SETD_PREC_F64) return pack_matrix_f64(M, n, scale, mu == 0, (double*)out, s);
   if (prec == SETD_PREC_F32) return pack_matrix_f32(M, n, scale, mu == 0, (float*)out, s);
+  if (prec == SETD_PREC_I8X4) return pack_matrix_i8(M, n, scale, out, s);
   return pack_matrix_bf16(M, n, scale, true, prec == SETD_PREC_BF16X3 ? 3 : 2, out, s);
 }
 
@@ -163,7 +165,7 @@ int setd::launch_f64_jobs(std::vector<ModeJob>& jobs, bool mode1, hipStream_t s)
 int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s) {
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) N *= dims[mu];
-  const DType mid = prec == SETD_PREC_F64 ? DType::F64 : DType::F32;
+  const DType mid = fp32_storage(prec) ? DType::F32 : DType::F64;
   const LaunchKind k1{true, prec, mid}, kb{false, prec, mid}, klast{false, prec, DType::F64};
   ModeJobs J;
   J.njobs = 0;
@@ -324,7 +326,7 @@ int build_bank(setd_ctx* c, hipStream_t s) {
 int setd::compute_gf(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, double* G, void* F) {
   const int d = c->d, nc = c->ncomp;
   const int64_t N = c->N;
-  const bool lp = c->prec != SETD_PREC_F64;
+  const bool lp = fp32_storage(c->prec);
   const DType tdt = lp ? DType::F32 : DType::F64;
   const size_t es = lp ? 4 : 8;
   if (G == nullptr) G = c->G;
@@ -366,7 +368,7 @@ int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, co
   const int64_t N = c->N;
   const double tau = c->tau;
   const int prec = c->prec;
-  const bool lp = prec != SETD_PREC_F64;
+  const bool lp = fp32_storage(prec);
   const DType tdt = lp ? DType::F32 : DType::F64;   // type of F, D and the intermediates
   const size_t es = lp ? 4 : 8;
   auto Fc_ = [&](int cc) { return (void*)((char*)b.F + cc * N * es); };
@@ -446,7 +448,7 @@ int step_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
 int step2_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
   const int d = c->d, nc = c->ncomp;
   const int64_t N = c->N;
-  const bool lp = c->prec != SETD_PREC_F64;
+  const bool lp = fp32_storage(c->prec);
   const DType tdt = lp ? DType::F32 : DType::F64;
   const size_t es = lp ? 4 : 8;
   SETD_TRY(compute_gf(c, u, gp, s));
@@ -685,7 +687,7 @@ size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec) {
   }
   if (!is_prec(prec)) return 0;
   // two ping-pong intermediates, plus the FP32 copy of V for reduced precision
-  const int nbuf = prec == SETD_PREC_F64 ? 2 : 3;
+  const int nbuf = fp32_storage(prec) ? 3 : 2;
   return pk + nbuf * round_up(N * (int64_t)sizeof(double), 256) + 256;
 }
 
@@ -737,7 +739,7 @@ int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, co
   if (nm == 0) {
     return launch_axpby(V, W, N, alpha, beta == 0.0 ? 0.0 : 1.0, s);
   }
-  const bool lp = prec != SETD_PREC_F64;
+  const bool lp = fp32_storage(prec);
   const int64_t fb = round_up(N * 8, 256);
   char* q = (char*)round_up((int64_t)(uintptr_t)wsp, 256);
   void* buf[3] = {q, q + fb, q + 2 * fb};
@@ -941,7 +943,7 @@ int setd_split_phi_apply(setd_ctx* c, int comp, int ell, int stage, const double
   }
   const Splitting& S = c->sp[ell];
   const void* src = V;
-  if (c->prec != SETD_PREC_F64) {   // reduced precision: round the input to FP32 once
+  if (fp32_storage(c->prec)) {   // FP32 forms: round the input to FP32 once
     SETD_TRY(launch_copy_convert(V, c->aux, c->N, DType::F32, s));
     src = c->aux;
   }

@@ -1,0 +1,179 @@
+"""The error-free int8 slicing form (SETD_PREC_I8X4) against the FP64 oracle.
+
+Each phi row and each tensor fibre is truncated to 30 bits of its largest
+entry and the digit products of order >= 3 are summed exactly, so a mode
+product errs by at most about n 2^-29 |x|max |p|max, independent of any
+cancellation in the sum.  Kernel checks use 1e-7 relative to the largest
+output entry (random data: the sums are ~sqrt(n) |x||p|, so the expected error
+is ~sqrt(n) 2^-29 ~ 3e-8 of it).  The integrator is held to the
+reduced-precision bar of the benchmark, 1e-5 relative L2 per field, on the
+same grids as the FP32 forms, and on the full 200-step 256^3 trajectory
+against the oracle's stored values.
+"""
+import glob
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import dev, host, rel_err, rel_l2, say, torch
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+import paper_2310_07551_amd as setd   # noqa: E402
+
+I8 = setd.PREC_I8X4
+KTOL = 1e-7
+TOL = 1e-5
+
+
+@pytest.mark.parametrize("dims", [(7, 13, 5), (64, 96), (100, 37, 20), (128, 128, 128), (33, 40), (256, 3, 40),
+                                  (300, 17), (20, 520), (64, 64, 300), (1, 9, 4)])
+def test_tucker_i8(dims):
+    """Every mode regime, ragged sizes (not multiples of 64 or of the 32
+    columns of a workgroup), contractions beyond one 256-value chunk and
+    beyond one 256-row group, alpha and beta."""
+    T = wl.random_tensor(dims, 2)
+    Ls = [wl.random_matrix(n, 20 + k, scale=1.0 / np.sqrt(n)) for k, n in enumerate(dims)]
+    W0 = wl.random_tensor(dims, 3)
+    Wd = dev(W0)
+    say("tucker i8", dims)
+    setd.tucker_apply(dev(T), Wd, dims, [dev(L) for L in Ls], alpha=0.7, beta=1.0, prec=I8)
+    ref = 0.7 * oracle.tucker(T, Ls)
+    e = rel_err(host(Wd, dims) - W0, ref)
+    say("  rel %.3e" % e)
+    assert e < KTOL, (dims, e)
+
+
+def test_single_modes_i8():
+    dims = (48, 40, 36)
+    T = wl.random_tensor(dims, 5)
+    for mu in (1, 2, 3):
+        L = wl.random_matrix(dims[mu - 1], 7 + mu, scale=0.2)
+        mats = [None] * 3
+        mats[mu - 1] = dev(L)
+        Wd = torch().empty(int(np.prod(dims)), dtype=torch().float64, device="cuda")
+        setd.tucker_apply(dev(T), Wd, dims, mats, prec=I8)
+        e = rel_err(host(Wd, dims), oracle.mode_product(T, L, mu))
+        assert e < KTOL, (mu, e)
+
+
+def test_i8_exact_on_representable_operands():
+    """Operands that are small integers times powers of two have exact
+    digits, so the product is exact (the accumulation rounds nowhere)."""
+    dims = (64, 96)
+    rng = np.random.default_rng(4)
+    T = rng.integers(-1000, 1000, size=dims).astype(np.float64) * 2.0 ** -7
+    L = rng.integers(-100, 100, size=(64, 64)).astype(np.float64) * 2.0 ** 3
+    Wd = torch().empty(int(np.prod(dims)), dtype=torch().float64, device="cuda")
+    setd.tucker_apply(dev(T), Wd, dims, [dev(L), None], prec=I8)
+    assert np.array_equal(host(Wd, dims), L @ T)
+
+
+def test_i8_wide_dynamic_range_and_cancellation():
+    """A fibre whose entries span 1e-8 .. 1 and sums that cancel to 1e-6 of
+    their terms: the error is bounded by the largest entries, not the result."""
+    n = 256
+    rng = np.random.default_rng(6)
+    T = rng.standard_normal((n, 64)) * 10.0 ** rng.uniform(-8, 0, size=(n, 64))
+    L = rng.standard_normal((n, n))
+    Wd = torch().empty(n * 64, dtype=torch().float64, device="cuda")
+    setd.tucker_apply(dev(T), Wd, (n, 64), [dev(L), None], prec=I8)
+    got = host(Wd, (n, 64))
+    ref = L @ T
+    # per term: operand truncations 2 x 2^-29 and the dropped digit pairs 12 x 2^-30 of |x|max |p|max
+    bound = n * 2.0 ** -26 * np.abs(L).max(axis=1)[:, None] * np.abs(T).max(axis=0)[None, :]
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_i8_nonfinite_input_propagates():
+    dims = (40, 30)
+    T = wl.random_tensor(dims, 7)
+    T[5, 3] = np.nan
+    L = wl.random_matrix(40, 8)
+    Wd = torch().empty(int(np.prod(dims)), dtype=torch().float64, device="cuda")
+    setd.tucker_apply(dev(T), Wd, dims, [dev(L), None], prec=I8)
+    got = host(Wd, dims)
+    assert np.all(np.isnan(got[:, 3]))
+    assert np.all(np.isfinite(np.delete(got, 3, axis=1)))
+
+
+def _run(prob, nsteps):
+    A = [[dev(M) for M in Ac] for Ac in prob.A]
+    ctx = setd.Context(prob.dims, A, prob.tau, prec=I8)
+    u = torch().from_numpy(prob.u0_flat()).to("cuda")
+    ctx.step(u, nsteps, prob.g_kind, prob.params)
+    torch().cuda.synchronize()
+    out = u.cpu().numpy()
+    return [out[c * prob.N:(c + 1) * prob.N].reshape(prob.dims, order="F") for c in range(2)]
+
+
+@pytest.mark.parametrize("case", ["schnak64", "fhn_ragged", "fhn128", "fhn_thin256", "fhn256"])
+def test_integrator_i8(case):
+    if case == "schnak64":
+        prob, steps = wl.make("schnakenberg2d_64"), 50
+    elif case == "fhn_ragged":
+        prob, steps = wl.fhn_3d(dims=(21, 17, 13)), 10
+    elif case == "fhn128":
+        prob, steps = wl.make("fhn3d_128"), 4
+    elif case == "fhn_thin256":
+        prob, steps = wl.fhn_3d(dims=(16, 8, 256)), 3
+    else:
+        prob, steps = wl.make("fhn3d_256"), 1
+    say("i8", case, steps)
+    got = _run(prob, steps)
+    ref = oracle.integrate(prob.U0, prob.A, prob.tau, steps, prob.g_kind, prob.params)
+    for c in range(2):
+        e = rel_l2(got[c], ref[c])
+        say("  field %d rel_l2 %.3e" % (c, e))
+        assert e < TOL, (case, c, e)
+
+
+def test_split_phi_apply_i8():
+    prob = wl.fhn_3d(dims=(20, 18, 16))
+    A = [[dev(M) for M in Ac] for Ac in prob.A]
+    ctx = setd.Context(prob.dims, A, prob.tau, prec=I8)
+    bank = oracle.etd.PhiBank(prob.A[0], prob.tau)
+    V = wl.random_tensor(prob.dims, 9)
+    Wd = torch().zeros(prob.N, dtype=torch().float64, device="cuda")
+    ctx.split_phi_apply(0, 2, setd.STAGE_F, dev(V), Wd, scale=1.0, beta=0.0)
+    assert rel_l2(host(Wd, prob.dims), bank.split_apply(2, "f", V)) < KTOL * 10
+
+
+def _stored(n):
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_fhn3d_goldens", os.path.join(here, "make_fhn3d_goldens.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    files = sorted(glob.glob(os.path.join(here, "fhn3d_%d_step*.txt" % n)))
+    assert files
+    return [mod.read_golden(f) for f in files]
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_i8_trajectory_against_stored_oracle(n):
+    """The whole trajectory of fhn3d_128 (100 steps) and of the 256^3
+    benchmark workload (200 steps) in the int8 form, against the FP64
+    oracle's stored values at every stored step count: 1e-5 over the sampled
+    points (relative L2 and max) and on the whole-field norms."""
+    prob = wl.make("fhn3d_%d" % n)
+    A = [[dev(M) for M in Ac] for Ac in prob.A]
+    ctx = setd.Context(prob.dims, A, prob.tau, prec=I8)
+    u = torch().from_numpy(prob.u0_flat()).to("cuda")
+    done = 0
+    for step, norms, idx, vals in _stored(n):
+        ctx.step(u, step - done, prob.g_kind, prob.params)
+        torch().cuda.synchronize()
+        done = step
+        x = u.cpu().numpy()
+        for c, name in enumerate(("u", "v")):
+            f = x[c * prob.N:(c + 1) * prob.N]
+            got, ref = f[idx], vals[:, c]
+            e2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            ei = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+            en = abs(np.linalg.norm(f) - norms[(name, "l2")]) / norms[(name, "l2")]
+            say("  step %d field %s: samples rel_l2 %.3e rel_inf %.3e norm %.3e" % (step, name, e2, ei, en))
+            assert e2 < TOL and ei < TOL and en < TOL, (n, step, name, e2, ei, en)
