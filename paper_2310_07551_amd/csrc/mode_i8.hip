@@ -74,17 +74,24 @@ __device__ __forceinline__ uint32_t digit_word(double x, int E) {
   return (uint32_t)(q + 0x00808080) ^ 0x00808080u;
 }
 
-// Byte k of w0..w3 gathered into one word (plane k of four consecutive values).
-__device__ __forceinline__ uint32_t plane_word(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int k) {
-  const int sh = 8 * k;
-  return ((w0 >> sh) & 0xffu) | (((w1 >> sh) & 0xffu) << 8) | (((w2 >> sh) & 0xffu) << 16) |
-         (((w3 >> sh) & 0xffu) << 24);
+// 4 x 4 byte transpose: d[k] gathers byte k of w0..w3 (digit plane k of four
+// consecutive values).  v_perm_b32 selects bytes of {S0, S1}, S1 as bytes 0-3.
+__device__ __forceinline__ void digit_planes(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t (&d)[4]) {
+  const uint32_t lo01 = __builtin_amdgcn_perm(w1, w0, 0x05010400u);   // w0.b0 w1.b0 w0.b1 w1.b1
+  const uint32_t hi01 = __builtin_amdgcn_perm(w1, w0, 0x07030602u);   // w0.b2 w1.b2 w0.b3 w1.b3
+  const uint32_t lo23 = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+  const uint32_t hi23 = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+  d[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+  d[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+  d[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+  d[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
 }
 
 // ---- packing of the matrix operand ----
-// out: four planes of ldp x ldp int8 (plane k = digit t_k), row-major
-// (row i, contraction index p contiguous), then ldp int32 row exponents.
-// One 256-thread block per row.
+// out: ldp rows of 4 ldp bytes, then ldp int32 row exponents.  Row i holds,
+// for every run of 16 contraction indices, the 16 bytes of digit t0, then of
+// t1, t2 and t3 (64 bytes): a lane's four digit operands of one k-step are
+// one 64-byte block.  One 256-thread block per row.
 __global__ void __launch_bounds__(256) pack_i8_kernel(const double* __restrict__ M, int n, int ldp, double scale,
                                                        uint8_t* __restrict__ out) {
   const int i = blockIdx.x;
@@ -105,14 +112,14 @@ __global__ void __launch_bounds__(256) pack_i8_kernel(const double* __restrict__
   m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   const bool finite = isfinite(m);
   const int E = finite ? exp_above(m) : kBadExp;
-  const int64_t plane = (int64_t)ldp * ldp;
+  uint8_t* row = out + (int64_t)i * 4 * ldp;
   for (int p = threadIdx.x; p < ldp; p += 256) {
     const double v = (i < n && p < n && finite) ? scale * M[i + (int64_t)n * p] : 0.0;
     const uint32_t w = finite ? digit_word(v, E) : 0u;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k * plane + (int64_t)i * ldp + p] = (uint8_t)(w >> (8 * k));
+    for (int k = 0; k < 4; ++k) row[(p >> 4) * 64 + 16 * k + (p & 15)] = (uint8_t)(w >> (8 * k));
   }
-  if (threadIdx.x == 0) ((int*)(out + 4 * plane))[i] = E;
+  if (threadIdx.x == 0) ((int*)(out + (int64_t)4 * ldp * ldp))[i] = E;
 }
 
 __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
@@ -158,6 +165,31 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
   const int64_t cc_p = c0 + pc;
   const bool col_ok = cc_p < ncols;
   const bool vec = MODE1 && (n % 2 == 0);   // 16-byte loads of a column (n even: aligned)
+  // the 16 values of column pc at kc + 32 ps + 16 h .. +15 (0 outside the tensor)
+  auto load16 = [&](const double* __restrict__ X, int kc, int h, double* v) {
+    const int k0 = kc + 32 * ps + 16 * h;
+    if (MODE1) {
+      const double* src = X + k0 + (int64_t)n * (col_ok ? cc_p : 0);
+      if (vec && col_ok && k0 + 16 <= n) {
+#pragma unroll
+        for (int j = 0; j < 16; j += 2) {
+          const d2 w = *(const d2*)(src + j);
+          v[j] = w[0];
+          v[j + 1] = w[1];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = (col_ok && k0 + j < n) ? src[j] : 0.0;
+      }
+    } else {
+      const double* src = X + (col_ok ? cc_p : 0) + slab + na * (int64_t)k0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        v[j] = (col_ok && k0 + j < n) ? *src : 0.0;
+        src += na;
+      }
+    }
+  };
   // the 32 values of column pc at kc + 32 ps .. +31 (0 outside the tensor)
   auto load32 = [&](const double* __restrict__ X, int kc, double (&v)[32]) {
     const int k0 = kc + 32 * ps;
@@ -189,12 +221,12 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
     uint8_t* dst = lds + pc * kLdsRow + 32 * ps;
 #pragma unroll
     for (int j = 0; j < 32; j += 4) {
-      uint32_t w[4];
+      uint32_t w[4], d[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) w[q] = ok ? digit_word(v[j + q], E) : 0u;
+      digit_planes(w[0], w[1], w[2], w[3], d);
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        *(uint32_t*)(dst + k * kCols * kLdsRow + j) = plane_word(w[0], w[1], w[2], w[3], k);
+      for (int k = 0; k < 4; ++k) *(uint32_t*)(dst + k * kCols * kLdsRow + j) = d[k];
     }
   };
 
@@ -209,7 +241,7 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
   for (int term = 0; term < jb.nterms; ++term) {
     const double* __restrict__ X = (const double*)jb.X[term];
     const uint8_t* __restrict__ P = (const uint8_t*)jb.P[term];
-    const int* __restrict__ Pexp = (const int*)(P + 4 * plane);
+    const int* __restrict__ Pexp = (const int*)(P + 4 * plane);   // after the ldp rows of 4 ldp bytes
     const double sc = jb.scale[term];
     const bool one_chunk = n <= kChunk;
 
@@ -218,22 +250,23 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
     double* myraw = raw + (pc * 8 + ps) * kRawRow;
     __syncthreads();   // the previous term's readers of colexp / lds / raw are done
     {
-      double m = 0.0;
-      bool bad = false;
-      for (int kc = 0; kc < n; kc += kChunk) {
-        double v[32];
-        load32(X, kc, v);
+      double m = 0.0, z = 0.0;   // z = sum of 0 * v: NaN iff some value is not finite
+      for (int kc = 0; kc < n; kc += kChunk)
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
-          bad = bad || !isfinite(v[j]);
-          m = fmax(m, fabs(v[j]));
-        }
-        if (one_chunk) {
+        for (int h = 0; h < 2; ++h) {
+          double v[16];
+          load16(X, kc, h, v);
 #pragma unroll
-          for (int j = 0; j < 32; j += 2) *(d2*)(myraw + j) = d2{v[j], v[j + 1]};
+          for (int j = 0; j < 16; ++j) {
+            z = fma(0.0, v[j], z);
+            m = fmax(m, fabs(v[j]));
+          }
+          if (one_chunk) {
+#pragma unroll
+            for (int j = 0; j < 16; j += 2) *(d2*)(myraw + 16 * h + j) = d2{v[j], v[j + 1]};
+          }
         }
-      }
-      red[ps][pc] = bad ? __builtin_inf() : m;
+      red[ps][pc] = z != z ? __builtin_inf() : m;
     }
     __syncthreads();
     if (tid < kCols) {
@@ -252,7 +285,7 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
 
     for (int kc = 0; kc < n; kc += kChunk) {
       __syncthreads();   // colexp written; the previous chunk's readers are done
-      // phase 2: digit planes of this chunk (the values are still in v when
+      // phase 2: digit planes of this chunk (the values are still in LDS when
       // the contraction is one chunk long)
       {
         double v[32];
@@ -269,17 +302,21 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
         split32(v, colexp[pc]);
       }
       __syncthreads();
-      // phase 3: this wave's 64 rows against the 32 columns
+      // phase 3: this wave's 64 rows against the 32 columns, 64 k per step
       if (active) {
-        const uint8_t* prow = P + (int64_t)(row0 + 64 * wave + l) * ldp + kc + 16 * g;
+        const uint8_t* prow = P + (int64_t)(row0 + 64 * wave + l) * 4 * ldp + (kc / 16 + g) * 64;
+        const int64_t mstride = (int64_t)16 * 4 * ldp;
         const int kend = n - kc < kChunk ? n - kc : kChunk;
         auto load_a = [&](int k64, int m, v4i (&a)[4]) {
+          const uint8_t* q = prow + m * mstride + 4 * k64;
 #pragma unroll
-          for (int s = 0; s < 4; ++s) a[s] = *(const v4i*)(prow + s * plane + (int64_t)16 * m * ldp + k64);
+          for (int s = 0; s < 4; ++s) a[s] = *(const v4i*)(q + 16 * s);
         };
         v4i acur[4], anext[4];
         load_a(0, 0, acur);
-        for (int k64 = 0; k64 < kend; k64 += 64) {
+#pragma unroll
+        for (int k64 = 0; k64 < kChunk; k64 += 64) {
+          if (k64 >= kend) break;
           v4i b[2][4];
 #pragma unroll
           for (int u = 0; u < 2; ++u)
