@@ -25,12 +25,13 @@
 // Operands: the phi matrices are sliced once when packed (four int8 planes,
 // row-major, plus each row's exponent); the tensor operand is FP64 and is
 // sliced in the kernel, once per workgroup: a workgroup owns 32 tensor
-// columns and up to 256 matrix rows (four waves of 64 rows).  Each thread
-// loads 32 values of one column at once; the block finds every column's
+// columns and up to 256 matrix rows (eight waves of 32 rows, two per SIMD, so
+// one wave's loads overlap the other's products).  Each thread loads 16
+// values of one column at once; the block finds every column's
 // exponent (phase 1), writes the columns' digit planes to LDS (phase 2), from
 // where every wave feeds them to v_mfma_i32_16x16x64_i8 against its own rows'
-// planes, each row block's matrix digits loading while the previous block's
-// products run (phase 3).
+// planes, the next 64-long step's matrix digits loading while the current
+// step's products run (phase 3).
 // Contractions longer than 256 take the columns 256 values at a time, the
 // exponent pass reading them once before.  Inputs, intermediates and outputs
 // stay FP64.
@@ -48,10 +49,16 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kCols = 32;               // tensor columns per workgroup
-constexpr int kRows = 256;              // matrix rows per workgroup (4 waves x 64)
+constexpr int kWaves = 8;               // waves per workgroup (two per SIMD)
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTM = 2;                  // 16-row blocks per wave
+constexpr int kWaveRows = 16 * kTM;
+constexpr int kRows = kWaves * kWaveRows;   // matrix rows per workgroup (256)
 constexpr int kChunk = 256;             // contraction values staged in LDS at a time
 constexpr int kLdsRow = kChunk + 16;    // bytes per (digit plane, column); +16 spreads the lanes over the banks
 constexpr int kBits = 30;
+constexpr int kVals = kCols * kChunk / kThreads;   // chunk values per thread in phases 1 and 2 (16)
+constexpr int kParts = kChunk / kVals;              // threads per column (16)
 constexpr int kBadExp = 1 << 14;        // marks a vector with a non-finite entry (its outputs become NaN)
 
 __device__ __forceinline__ v4i mfma_i8(const v4i& a, const v4i& b, const v4i& c) {
@@ -126,11 +133,12 @@ __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
   return (bid & 7) * per_xcd + (bid >> 3);
 }
 
-// One workgroup: rows row0 .. row0+255 of every term's matrix, 32 tensor
-// columns.  MODE1: column b holds X[p + n b] (contiguous); otherwise column
-// (a, b) holds X[a + na p + na n b].  Y = base + sum_t scale_t (P_t X_t).
+// One workgroup (8 waves, two per SIMD): rows row0 .. row0+255 of every
+// term's matrix (32 per wave), 32 tensor columns.  MODE1: column b holds
+// X[p + n b] (contiguous); otherwise column (a, b) holds X[a + na p + na n b].
+// Y = base + sum_t scale_t (P_t X_t).
 template <bool MODE1>
-__global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64_t per_xcd) {
+__global__ void __launch_bounds__(kThreads, 1) mode_i8_kernel(const ModeJobs J, int64_t per_xcd) {
   const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;   // uniform over the block
   const ModeJob& jb = J.job[find_job(J, t)];
@@ -147,80 +155,56 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
   const int row0 = it * kRows;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, l = lane & 15;
+  const int wrow = row0 + kWaveRows * wave;   // this wave's first row
   __shared__ __attribute__((aligned(16))) uint8_t lds[4 * kCols * kLdsRow];
-  __shared__ double red[8][kCols];
-  // the raw chunk, 32 contiguous values per thread role (pc, ps), rows padded
-  // by 16 bytes so that neighbouring lanes use different banks
-  constexpr int kRawRow = 34;
-  __shared__ __attribute__((aligned(16))) double raw[kCols * 8 * kRawRow];
+  __shared__ double red[kParts][kCols];
   __shared__ int colexp[kCols];
-  const bool active = row0 + 64 * wave < n;   // this wave has rows (ldp is a multiple of 64)
+  // the raw chunk: kVals contiguous values per thread role, rows padded by
+  // 16 bytes so that neighbouring lanes use different banks
+  constexpr int kRawRow = kVals + 2;
+  __shared__ __attribute__((aligned(16))) double raw[kThreads * kRawRow];
+  // rows of this wave exist (ldp and the row split are multiples of 32)
+  const bool active = wrow < n;
   const int64_t plane = (int64_t)ldp * ldp;
 
-  // Thread roles of phases 1 and 2: column pc, its values kc + 32 ps .. +31.
-  // MODE1 gives a column 8 neighbouring lanes (each a contiguous 256-byte
-  // run); otherwise 32 lanes read 32 neighbouring columns at one k.
-  const int pc = MODE1 ? (tid >> 3) : (tid & 31);
-  const int ps = MODE1 ? (tid & 7) : (tid >> 5);
+  // Thread roles of phases 1 and 2: column pc, its values kc + kVals ps ..
+  // +kVals-1.  MODE1 gives a column kParts neighbouring lanes (each a
+  // contiguous run); otherwise 32 lanes read 32 neighbouring columns at one k.
+  const int pc = MODE1 ? (tid / kParts) : (tid % kCols);
+  const int ps = MODE1 ? (tid % kParts) : (tid / kCols);
   const int64_t cc_p = c0 + pc;
   const bool col_ok = cc_p < ncols;
   const bool vec = MODE1 && (n % 2 == 0);   // 16-byte loads of a column (n even: aligned)
-  // the 16 values of column pc at kc + 32 ps + 16 h .. +15 (0 outside the tensor)
-  auto load16 = [&](const double* __restrict__ X, int kc, int h, double* v) {
-    const int k0 = kc + 32 * ps + 16 * h;
+  auto load_vals = [&](const double* __restrict__ X, int kc, double (&v)[kVals]) {
+    const int k0 = kc + kVals * ps;
     if (MODE1) {
       const double* src = X + k0 + (int64_t)n * (col_ok ? cc_p : 0);
-      if (vec && col_ok && k0 + 16 <= n) {
+      if (vec && col_ok && k0 + kVals <= n) {
 #pragma unroll
-        for (int j = 0; j < 16; j += 2) {
+        for (int j = 0; j < kVals; j += 2) {
           const d2 w = *(const d2*)(src + j);
           v[j] = w[0];
           v[j + 1] = w[1];
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = (col_ok && k0 + j < n) ? src[j] : 0.0;
+        for (int j = 0; j < kVals; ++j) v[j] = (col_ok && k0 + j < n) ? src[j] : 0.0;
       }
     } else {
       const double* src = X + (col_ok ? cc_p : 0) + slab + na * (int64_t)k0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < kVals; ++j) {
         v[j] = (col_ok && k0 + j < n) ? *src : 0.0;
         src += na;
       }
     }
   };
-  // the 32 values of column pc at kc + 32 ps .. +31 (0 outside the tensor)
-  auto load32 = [&](const double* __restrict__ X, int kc, double (&v)[32]) {
-    const int k0 = kc + 32 * ps;
-    if (MODE1) {
-      const double* src = X + k0 + (int64_t)n * (col_ok ? cc_p : 0);
-      if (vec && col_ok && k0 + 32 <= n) {
-#pragma unroll
-        for (int j = 0; j < 32; j += 2) {
-          const d2 w = *(const d2*)(src + j);
-          v[j] = w[0];
-          v[j + 1] = w[1];
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 32; ++j) v[j] = (col_ok && k0 + j < n) ? src[j] : 0.0;
-      }
-    } else {
-      const double* src = X + (col_ok ? cc_p : 0) + slab + na * (int64_t)k0;
-#pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        v[j] = (col_ok && k0 + j < n) ? *src : 0.0;
-        src += na;
-      }
-    }
-  };
-  // writes the digit planes of v to LDS (column pc, chunk offset 32 ps)
-  auto split32 = [&](const double (&v)[32], int E) {
+  // writes the digit planes of v to LDS (column pc, chunk offset kVals ps)
+  auto split_vals = [&](const double (&v)[kVals], int E) {
     const bool ok = E != kBadExp;
-    uint8_t* dst = lds + pc * kLdsRow + 32 * ps;
+    uint8_t* dst = lds + pc * kLdsRow + kVals * ps;
 #pragma unroll
-    for (int j = 0; j < 32; j += 4) {
+    for (int j = 0; j < kVals; j += 4) {
       uint32_t w[4], d[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) w[q] = ok ? digit_word(v[j + q], E) : 0u;
@@ -230,9 +214,9 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
     }
   };
 
-  double out[4][2][4];
+  double out[kTM][2][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < kTM; ++m)
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -247,106 +231,109 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
 
     // phase 1: exponent of every column (a one-chunk contraction keeps its
     // values in LDS for phase 2)
-    double* myraw = raw + (pc * 8 + ps) * kRawRow;
+    double* myraw = raw + tid * kRawRow;
     __syncthreads();   // the previous term's readers of colexp / lds / raw are done
     {
       double m = 0.0, z = 0.0;   // z = sum of 0 * v: NaN iff some value is not finite
-      for (int kc = 0; kc < n; kc += kChunk)
+      for (int kc = 0; kc < n; kc += kChunk) {
+        double v[kVals];
+        load_vals(X, kc, v);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          double v[16];
-          load16(X, kc, h, v);
-#pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            z = fma(0.0, v[j], z);
-            m = fmax(m, fabs(v[j]));
-          }
-          if (one_chunk) {
-#pragma unroll
-            for (int j = 0; j < 16; j += 2) *(d2*)(myraw + 16 * h + j) = d2{v[j], v[j + 1]};
-          }
+        for (int j = 0; j < kVals; ++j) {
+          z = fma(0.0, v[j], z);
+          m = fmax(m, fabs(v[j]));
         }
+        if (one_chunk) {
+#pragma unroll
+          for (int j = 0; j < kVals; j += 2) *(d2*)(myraw + j) = d2{v[j], v[j + 1]};
+        }
+      }
       red[ps][pc] = z != z ? __builtin_inf() : m;
     }
     __syncthreads();
     if (tid < kCols) {
       double m = red[0][tid];
-      for (int s = 1; s < 8; ++s) m = fmax(m, red[s][tid]);
+      for (int q = 1; q < kParts; ++q) m = fmax(m, red[q][tid]);
       colexp[tid] = isfinite(m) ? exp_above(m) : kBadExp;
     }
 
-    v4i acc[5][4][2];   // [order a + b - 2][row block][column block]
+    v4i acc[5][kTM][2];   // [order a + b - 2][row block][column block]
 #pragma unroll
     for (int o = 0; o < 5; ++o)
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < kTM; ++m)
 #pragma unroll
         for (int u = 0; u < 2; ++u) acc[o][m][u] = v4i{0, 0, 0, 0};
 
     for (int kc = 0; kc < n; kc += kChunk) {
       __syncthreads();   // colexp written; the previous chunk's readers are done
-      // phase 2: digit planes of this chunk (the values are still in LDS when
-      // the contraction is one chunk long)
+      // phase 2: digit planes of this chunk
       {
-        double v[32];
+        double v[kVals];
         if (one_chunk) {
 #pragma unroll
-          for (int j = 0; j < 32; j += 2) {
+          for (int j = 0; j < kVals; j += 2) {
             const d2 w = *(const d2*)(myraw + j);
             v[j] = w[0];
             v[j + 1] = w[1];
           }
         } else {
-          load32(X, kc, v);
+          load_vals(X, kc, v);
         }
-        split32(v, colexp[pc]);
+        split_vals(v, colexp[pc]);
       }
       __syncthreads();
-      // phase 3: this wave's 64 rows against the 32 columns, 64 k per step
+      // phase 3: this wave's rows against the 32 columns, 64 k per step; the
+      // next step's matrix digits load while this step's products run
       if (active) {
-        const uint8_t* prow = P + (int64_t)(row0 + 64 * wave + l) * 4 * ldp + (kc / 16 + g) * 64;
+        const uint8_t* prow = P + (int64_t)(wrow + l) * 4 * ldp + (kc / 16 + g) * 64;
         const int64_t mstride = (int64_t)16 * 4 * ldp;
         const int kend = n - kc < kChunk ? n - kc : kChunk;
-        auto load_a = [&](int k64, int m, v4i (&a)[4]) {
-          const uint8_t* q = prow + m * mstride + 4 * k64;
+        auto load_a = [&](int k64, v4i (&a)[kTM][4]) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s) a[s] = *(const v4i*)(q + 16 * s);
+          for (int m = 0; m < kTM; ++m) {
+            const uint8_t* q = prow + m * mstride + 4 * k64;
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) a[m][s2] = *(const v4i*)(q + 16 * s2);
+          }
         };
-        v4i acur[4], anext[4];
-        load_a(0, 0, acur);
+        v4i acur[kTM][4], anext[kTM][4];
+        load_a(0, acur);
 #pragma unroll
         for (int k64 = 0; k64 < kChunk; k64 += 64) {
           if (k64 >= kend) break;
+          if (k64 + 64 < kend) load_a(k64 + 64, anext);
           v4i b[2][4];
 #pragma unroll
           for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-              b[u][s] = *(const v4i*)(lds + (s * kCols + 16 * u + l) * kLdsRow + k64 + 16 * g);
+            for (int s2 = 0; s2 < 4; ++s2)
+              b[u][s2] = *(const v4i*)(lds + (s2 * kCols + 16 * u + l) * kLdsRow + k64 + 16 * g);
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            // the next row block's digits (the next step's first block after the last)
-            if (m < 3) load_a(k64, m + 1, anext);
-            else load_a(k64 + 64 < kend ? k64 + 64 : k64, 0, anext);
+          for (int m = 0; m < kTM; ++m)
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
+              const v4i* a = acur[m];
               // matrix digit pb (first operand), tensor digit pa, order pa + pb >= 2
-              acc[4][m][u] = mfma_i8(acur[3], b[u][3], acc[4][m][u]);
-              acc[3][m][u] = mfma_i8(acur[3], b[u][2], acc[3][m][u]);
-              acc[3][m][u] = mfma_i8(acur[2], b[u][3], acc[3][m][u]);
-              acc[2][m][u] = mfma_i8(acur[3], b[u][1], acc[2][m][u]);
-              acc[2][m][u] = mfma_i8(acur[2], b[u][2], acc[2][m][u]);
-              acc[2][m][u] = mfma_i8(acur[1], b[u][3], acc[2][m][u]);
-              acc[1][m][u] = mfma_i8(acur[3], b[u][0], acc[1][m][u]);
-              acc[1][m][u] = mfma_i8(acur[2], b[u][1], acc[1][m][u]);
-              acc[1][m][u] = mfma_i8(acur[1], b[u][2], acc[1][m][u]);
-              acc[1][m][u] = mfma_i8(acur[0], b[u][3], acc[1][m][u]);
-              acc[0][m][u] = mfma_i8(acur[2], b[u][0], acc[0][m][u]);
-              acc[0][m][u] = mfma_i8(acur[1], b[u][1], acc[0][m][u]);
-              acc[0][m][u] = mfma_i8(acur[0], b[u][2], acc[0][m][u]);
+              acc[4][m][u] = mfma_i8(a[3], b[u][3], acc[4][m][u]);
+              acc[3][m][u] = mfma_i8(a[3], b[u][2], acc[3][m][u]);
+              acc[3][m][u] = mfma_i8(a[2], b[u][3], acc[3][m][u]);
+              acc[2][m][u] = mfma_i8(a[3], b[u][1], acc[2][m][u]);
+              acc[2][m][u] = mfma_i8(a[2], b[u][2], acc[2][m][u]);
+              acc[2][m][u] = mfma_i8(a[1], b[u][3], acc[2][m][u]);
+              acc[1][m][u] = mfma_i8(a[3], b[u][0], acc[1][m][u]);
+              acc[1][m][u] = mfma_i8(a[2], b[u][1], acc[1][m][u]);
+              acc[1][m][u] = mfma_i8(a[1], b[u][2], acc[1][m][u]);
+              acc[1][m][u] = mfma_i8(a[0], b[u][3], acc[1][m][u]);
+              acc[0][m][u] = mfma_i8(a[2], b[u][0], acc[0][m][u]);
+              acc[0][m][u] = mfma_i8(a[1], b[u][1], acc[0][m][u]);
+              acc[0][m][u] = mfma_i8(a[0], b[u][2], acc[0][m][u]);
             }
+          if (k64 + 64 < kend) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acur[s] = anext[s];
+            for (int m = 0; m < kTM; ++m)
+#pragma unroll
+              for (int s2 = 0; s2 < 4; ++s2) acur[m][s2] = anext[m][s2];
           }
         }
       }
@@ -358,10 +345,10 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
       for (int u = 0; u < 2; ++u) {
         const int ex = colexp[16 * u + l];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < kTM; ++m)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int ep = Pexp[row0 + 64 * wave + 16 * m + 4 * g + r];
+            const int ep = Pexp[wrow + 16 * m + 4 * g + r];
             double w = (double)acc[0][m][u][r] * 0x1p-32;
             w = fma((double)acc[1][m][u][r], 0x1p-24, w);
             w = fma((double)acc[2][m][u][r], 0x1p-16, w);
@@ -381,10 +368,10 @@ __global__ void __launch_bounds__(256, 1) mode_i8_kernel(const ModeJobs J, int64
     const int64_t cc = c0 + 16 * u + l;
     if (cc >= ncols) continue;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < kTM; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = row0 + 64 * wave + 16 * m + 4 * g + r;
+        const int i = wrow + 16 * m + 4 * g + r;
         if (i >= n) continue;
         const int64_t o = MODE1 ? i + (int64_t)n * cc : cc + na * (int64_t)i + slab;
         Y[o] = base ? base[o] + out[m][u][r] : out[m][u][r];
@@ -426,9 +413,9 @@ int launch_mode_i8(ModeJobs& J, bool mode1, hipStream_t s) {
   const int64_t per = ceil_div(tot, 8);
   const dim3 grid((unsigned)(per * 8));
   if (mode1)
-    hipLaunchKernelGGL(mode_i8_kernel<true>, grid, dim3(256), 0, s, J, per);
+    hipLaunchKernelGGL(mode_i8_kernel<true>, grid, dim3(kThreads), 0, s, J, per);
   else
-    hipLaunchKernelGGL(mode_i8_kernel<false>, grid, dim3(256), 0, s, J, per);
+    hipLaunchKernelGGL(mode_i8_kernel<false>, grid, dim3(kThreads), 0, s, J, per);
   SETD_LAUNCHED();
   return SETD_OK;
 }
