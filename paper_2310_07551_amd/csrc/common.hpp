@@ -191,11 +191,14 @@ inline bool fp32_storage(int p) {
   return p == SETD_PREC_F32 || p == SETD_PREC_BF16X3 || p == SETD_PREC_BF16X2;
 }
 size_t packed_bytes(int n, int prec);
-// Error-free int8 slicing (mode_i8.hip): packed matrix size, packing, and the
-// mode-product launcher (FP64 tensors, any regime).
+// Error-free int8 slicing (mode_i8.hip): packed matrix size, packing, the
+// digit-buffer size of one FP64 input of N entries contracted along a mode of
+// size n, and the mode-product launcher (FP64 tensors, any regime), which
+// needs one digit buffer per distinct input of the launch in `ws`.
 size_t packed_bytes_i8(int n);
 int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t s);
-int launch_mode_i8(ModeJobs& jobs, bool mode1, hipStream_t s);
+size_t i8_digit_bytes(int64_t N, int n);
+int launch_mode_i8(ModeJobs& jobs, bool mode1, void* ws, size_t ws_bytes, hipStream_t s);
 
 // Pointwise helpers (pointwise.hip).
 int launch_axpby(const double* x, double* y, int64_t n, double a, double b, hipStream_t s);  // y = a x + b y

@@ -27,6 +27,7 @@ struct setd_ctx {
   double* Y1[2][9] = {};
   double* Y2[2][9] = {};
   double* aux = nullptr;         // FP32 copy of a split_phi_apply input (reduced precision)
+  setd::DevBuf i8_mem;           // int8 digit buffers of the Tucker inputs (SETD_PREC_I8X4)
   setd::DevBuf A_mem, stencil_mem, bank_mem, work_mem;
   // one captured step (hipGraph), replayed per step on an internal stream
   hipStream_t gstream = nullptr;
@@ -78,7 +79,12 @@ struct TuckerOut {
 // Runs all outputs of a group: d grouped launches (or more if a launch would
 // exceed kMaxJobs).  dims has d >= 2 entries.  With a reduced-precision
 // `prec`, term inputs and Y1/Y2 are FP32 and the outputs FP64.
-int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s);
+// SETD_PREC_I8X4 needs digit buffers for the inputs of a launch (i8ws: at
+// least i8_slots(d, nouts total terms) buffers of i8_slot_bytes each).
+int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s,
+                     void* i8ws = nullptr, size_t i8bytes = 0);
+// Bytes of one int8 digit buffer for any mode of the grid.
+size_t i8_slot_bytes(int d, const int* dims);
 // Packs a matrix for the mode kernels of the given arithmetic and direction.
 int pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s);
 // G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type,

@@ -22,23 +22,23 @@
 // 1e5 times the step's result: their FP32 partial sums round at the scale of
 // the terms.
 //
-// Operands: the phi matrices are sliced once when packed (four int8 planes,
-// row-major, plus each row's exponent); the tensor operand is FP64 and is
-// sliced in the kernel, once per workgroup: a workgroup owns 32 tensor
-// columns and up to 256 matrix rows (eight waves of 32 rows, two per SIMD, so
-// one wave's loads overlap the other's products).  Each thread loads 16
-// values of one column at once; the block finds every column's
-// exponent (phase 1), writes the columns' digit planes to LDS (phase 2), from
-// where every wave feeds them to v_mfma_i32_16x16x64_i8 against its own rows'
-// planes, the next 64-long step's matrix digits loading while the current
-// step's products run (phase 3).
-// Contractions longer than 256 take the columns 256 values at a time, the
-// exponent pass reading them once before.  Inputs, intermediates and outputs
-// stay FP64.
+// Two kernels.  The slicing kernel reads an FP64 tensor operand once and
+// writes, for every fibre along the contracted mode, its exponent and its
+// four digit planes (4 bytes per entry, zero beyond n) in the order the
+// matrix cores read them; it is bound by HBM and does all the splitting work.
+// The digit GEMM then multiplies the phi digits (sliced once when the matrix
+// is packed) with those planes: a workgroup of 8 waves (two per SIMD) keeps a
+// 64-row panel of the matrix digits in LDS and each wave computes a 64-row x
+// 16-column output tile from it, reading its columns' digits straight from
+// memory (64 contiguous bytes per lane and k-step, the next step's in flight
+// during the current one's products).  Its main loop is loads and MFMAs only;
+// the FP64 combination runs once per output.  Inputs, intermediates and
+// outputs stay FP64.
 //
 // Lane layout (probed on gfx950): lane (g, l) supplies row l of A and column
 // l of B at 16 k-slots (g, j); both operands use k = 16 g + j of the current
 // 64-long k-step, and register r of lane (g, l) holds D[4 g + r][l].
+#include <algorithm>
 #include <cstdint>
 
 #include "common.hpp"
@@ -48,18 +48,28 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kCols = 32;               // tensor columns per workgroup
-constexpr int kWaves = 8;               // waves per workgroup (two per SIMD)
-constexpr int kThreads = 64 * kWaves;
-constexpr int kTM = 2;                  // 16-row blocks per wave
-constexpr int kWaveRows = 16 * kTM;
-constexpr int kRows = kWaves * kWaveRows;   // matrix rows per workgroup (256)
-constexpr int kChunk = 256;             // contraction values staged in LDS at a time
-constexpr int kLdsRow = kChunk + 16;    // bytes per (digit plane, column); +16 spreads the lanes over the banks
 constexpr int kBits = 30;
-constexpr int kVals = kCols * kChunk / kThreads;   // chunk values per thread in phases 1 and 2 (16)
-constexpr int kParts = kChunk / kVals;              // threads per column (16)
 constexpr int kBadExp = 1 << 14;        // marks a vector with a non-finite entry (its outputs become NaN)
+// slicing kernel: 32 fibres per 256-thread workgroup, 8 threads per fibre,
+// each 32 consecutive values of a 256-long chunk
+constexpr int kSliceCols = 32;
+constexpr int kSliceChunk = 256;
+constexpr int kStageRow = 4 * kSliceChunk + 16;   // LDS row of one fibre's digits, padded against bank conflicts
+// digit GEMM: 8 waves x (64 rows x 16 columns); the matrix panel holds 64
+// rows x 256 contraction values (4 bytes each), rows padded by 16 bytes so
+// that neighbouring lanes read different banks
+constexpr int kGemmWaves = 8;
+constexpr int kPanelRows = 64;
+constexpr int kWaveCols = 16;
+constexpr int kGroupCols = kGemmWaves * kWaveCols;   // 128 columns per workgroup
+constexpr int kPanelK = 256;
+constexpr int kPanelRow = 4 * kPanelK + 16;
+#ifndef SETD_I8_WG_PER_CU
+#define SETD_I8_WG_PER_CU 12
+#endif
+constexpr int64_t kCus = 256;
+constexpr int64_t kGemmWgPerCu = SETD_I8_WG_PER_CU;   // workgroups per compute unit a launch aims at
+constexpr int64_t kMaxSup = 16;                       // longest run of column groups
 
 __device__ __forceinline__ v4i mfma_i8(const v4i& a, const v4i& b, const v4i& c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
@@ -133,249 +143,355 @@ __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
   return (bid & 7) * per_xcd + (bid >> 3);
 }
 
-// One workgroup (8 waves, two per SIMD): rows row0 .. row0+255 of every
-// term's matrix (32 per wave), 32 tensor columns.  MODE1: column b holds
-// X[p + n b] (contiguous); otherwise column (a, b) holds X[a + na p + na n b].
-// Y = base + sum_t scale_t (P_t X_t).
+// ---- slicing kernel ----
+// Job j: X[0] = FP64 tensor, Y = digit buffer.  MODE1: fibre b holds
+// X[p + n b] (p contiguous); otherwise fibre c = a + na b holds
+// X[a + na p + na n b].  Fibre c's planes: D + c 4 ldp, value p's digit s at
+// (p / 16) 64 + 16 s + p % 16; then one int32 exponent per fibre.
+// A workgroup slices 32 fibres that are consecutive in the digit buffer, 256
+// values at a time, each thread 32 values of one fibre.  The digit planes are
+// assembled in LDS and leave as whole fibre rows (1 KB per fibre and chunk),
+// so every store of a wave covers contiguous memory.  For n <= 256 each value
+// is read once: it stays in registers between the maximum and the digits.
 template <bool MODE1>
-__global__ void __launch_bounds__(kThreads, 1) mode_i8_kernel(const ModeJobs J, int64_t per_xcd) {
+__global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t per_xcd) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[kSliceCols * kStageRow];
+  __shared__ double red[8][kSliceCols];
+  __shared__ int colexp[kSliceCols];
+  const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
+  if (t >= J.total_tiles) return;   // uniform over the block
+  const ModeJob& jb = J.job[find_job(J, t)];
+  const int64_t lt = t - jb.tile_begin;
+  const int n = jb.n, ldp = jb.ldp;
+  const int64_t na = jb.na, nb = jb.nb;
+  const int64_t nfib = MODE1 ? nb : na;   // fibres per slab
+  const int64_t ct = MODE1 ? lt : lt % jb.tiles_a;
+  const int64_t bslab = MODE1 ? 0 : lt / jb.tiles_a;
+  const int tid = threadIdx.x;
+  const int pc = MODE1 ? (tid >> 3) : (tid & 31);   // fibre of this thread
+  const int ps = MODE1 ? (tid & 7) : (tid >> 5);    // its 32-value block of a chunk
+  const int64_t fa0 = ct * kSliceCols;
+  const int nv = (int)(nfib - fa0 < kSliceCols ? nfib - fa0 : kSliceCols);   // fibres of this workgroup
+  const bool ok = pc < nv;
+  const int64_t fa = fa0 + (ok ? pc : 0);
+  const double* __restrict__ X = (const double*)jb.X[0];
+  const double* src = MODE1 ? X + (int64_t)n * fa : X + fa + na * (int64_t)n * bslab;
+  const int64_t step = MODE1 ? 1 : na;
+  const int64_t fib0 = MODE1 ? fa0 : fa0 + na * bslab;
+  const int64_t ntot = MODE1 ? nb : na * nb;
+  uint8_t* __restrict__ D = (uint8_t*)jb.Y;
+  int* __restrict__ Dexp = (int*)(D + ntot * 4 * (int64_t)ldp);
+  double v[32];
+  auto load = [&](int kc) {
+    const int k0 = kc + 32 * ps;
+    if (MODE1 && ok && (n % 2 == 0) && k0 + 32 <= n) {
+#pragma unroll
+      for (int j = 0; j < 32; j += 2) {
+        const d2 w = *(const d2*)(src + k0 + j);
+        v[j] = w[0];
+        v[j + 1] = w[1];
+      }
+    } else {
+      const double* p = src + step * k0;
+#pragma unroll
+      for (int j = 0; j < 32; ++j) v[j] = (ok && k0 + j < n) ? p[step * j] : 0.0;
+    }
+  };
+  // the fibre's largest magnitude (z = sum of 0 * v: NaN iff some value is not finite)
+  double m = 0.0, z = 0.0;
+  for (int kc = 0; kc < n; kc += kSliceChunk) {
+    load(kc);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      z = fma(0.0, v[j], z);
+      m = fmax(m, fabs(v[j]));
+    }
+  }
+  red[ps][pc] = z != z ? __builtin_inf() : m;
+  __syncthreads();
+  if (tid < kSliceCols) {
+    double mm = red[0][tid];
+    for (int q = 1; q < 8; ++q) mm = fmax(mm, red[q][tid]);
+    const int e = isfinite(mm) ? exp_above(mm) : kBadExp;
+    colexp[tid] = e;
+    if (tid < nv) Dexp[fib0 + tid] = e;
+  }
+  __syncthreads();
+  const int E = colexp[pc];
+  const bool finite = E != kBadExp;
+  for (int kc = 0; kc < ldp; kc += kSliceChunk) {
+    if (n > kSliceChunk) load(kc);   // otherwise v still holds the only chunk
+    const int kw = ldp - kc < kSliceChunk ? ldp - kc : kSliceChunk;   // multiple of 64
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int run = 2 * ps + h;
+      if (16 * run >= kw) break;
+      uint32_t d[4][4];   // [group of 4 values][plane]
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = finite ? digit_word(v[16 * h + 4 * q + e], E) : 0u;
+        digit_planes(w[0], w[1], w[2], w[3], d[q]);
+      }
+      uint8_t* o = stage + pc * kStageRow + 64 * run;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+        *(v4i*)(o + 16 * sp) = v4i{(int)d[0][sp], (int)d[1][sp], (int)d[2][sp], (int)d[3][sp]};
+    }
+    __syncthreads();
+    const int units = kw / 4;   // 16-byte units per fibre row of this chunk
+    for (int e = tid; e < nv * units; e += 256) {
+      const int f = e / units, u = e - f * units;
+      *(v4i*)(D + (fib0 + f) * 4 * (int64_t)ldp + 4 * kc + 16 * u) = *(const v4i*)(stage + f * kStageRow + 16 * u);
+    }
+    __syncthreads();   // the stage is rewritten by the next chunk
+  }
+}
+
+// ---- digit GEMM ----
+// Job j: X[t] = digit buffer of term t (slicing kernel layout), P[t] = packed
+// matrix digits, Y = base + sum_t scale_t P_t X_t.  A workgroup owns row
+// panel `it` (64 rows) and a run of `sup` consecutive column groups of 128
+// (for modes >= 2 the groups of all slabs in order, tiles_a per slab).  It
+// walks the items (group, term, 256-chunk of the contraction) of its run as
+// one software pipeline: the tensor digits of the next k-step are always in
+// flight, across item and group boundaries, and when the next item needs
+// another matrix panel (several terms, or n > 256) that panel is fetched
+// during the current item into the second LDS buffer (SWAP; the host picks
+// it when some job has several terms or n > 256).  Without SWAP the panel is
+// loaded once and the loop has no barrier at all.
+template <bool MODE1, bool SWAP>
+__global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64_t per_xcd, int sup) {
+  __shared__ __attribute__((aligned(16))) uint8_t panel[2][kPanelRows * kPanelRow];
+  __shared__ int pexp[2][kPanelRows];
   const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;   // uniform over the block
   const ModeJob& jb = J.job[find_job(J, t)];
   const int64_t lt = t - jb.tile_begin;
   const int it = (int)(lt % jb.tiles_i);
-  const int64_t rest = lt / jb.tiles_i;
   const int n = jb.n, ldp = jb.ldp;
+  const int nterms = SWAP ? jb.nterms : 1;   // without SWAP the host guarantees one term, n <= 256
   const int64_t na = jb.na, nb = jb.nb;
-  const int64_t ct = MODE1 ? rest : rest % jb.tiles_a;   // column tile
-  const int64_t bslab = MODE1 ? 0 : rest / jb.tiles_a;   // b of the column tile (modes >= 2)
-  const int64_t c0 = ct * kCols;                          // first b (mode 1) or a (modes >= 2)
-  const int64_t ncols = MODE1 ? nb : na;
-  const int64_t slab = MODE1 ? 0 : na * (int64_t)n * bslab;
-  const int row0 = it * kRows;
-
+  const int64_t nfib = MODE1 ? nb : na;
+  const int64_t ntot = MODE1 ? nb : na * nb;
+  const int64_t ngroups = (int64_t)jb.tiles_a * (MODE1 ? 1 : nb);
+  const int64_t grp0 = (lt / jb.tiles_i) * sup;
+  const int ngrp = (int)(ngroups - grp0 < sup ? ngroups - grp0 : sup);
+  const int nch = SWAP ? (n + kPanelK - 1) / kPanelK : 1;   // 256-chunks of the contraction
+  const int nitems = ngrp * nterms * nch;
+  const int row0 = it * kPanelRows;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, l = lane & 15;
-  const int wrow = row0 + kWaveRows * wave;   // this wave's first row
-  __shared__ __attribute__((aligned(16))) uint8_t lds[4 * kCols * kLdsRow];
-  __shared__ double red[kParts][kCols];
-  __shared__ int colexp[kCols];
-  // the raw chunk: kVals contiguous values per thread role, rows padded by
-  // 16 bytes so that neighbouring lanes use different banks
-  constexpr int kRawRow = kVals + 2;
-  __shared__ __attribute__((aligned(16))) double raw[kThreads * kRawRow];
-  // rows of this wave exist (ldp and the row split are multiples of 32)
-  const bool active = wrow < n;
-  const int64_t plane = (int64_t)ldp * ldp;
+  const int64_t rowbytes = 4 * (int64_t)ldp;
 
-  // Thread roles of phases 1 and 2: column pc, its values kc + kVals ps ..
-  // +kVals-1.  MODE1 gives a column kParts neighbouring lanes (each a
-  // contiguous run); otherwise 32 lanes read 32 neighbouring columns at one k.
-  const int pc = MODE1 ? (tid / kParts) : (tid % kCols);
-  const int ps = MODE1 ? (tid % kParts) : (tid / kCols);
-  const int64_t cc_p = c0 + pc;
-  const bool col_ok = cc_p < ncols;
-  const bool vec = MODE1 && (n % 2 == 0);   // 16-byte loads of a column (n even: aligned)
-  auto load_vals = [&](const double* __restrict__ X, int kc, double (&v)[kVals]) {
-    const int k0 = kc + kVals * ps;
-    if (MODE1) {
-      const double* src = X + k0 + (int64_t)n * (col_ok ? cc_p : 0);
-      if (vec && col_ok && k0 + kVals <= n) {
-#pragma unroll
-        for (int j = 0; j < kVals; j += 2) {
-          const d2 w = *(const d2*)(src + j);
-          v[j] = w[0];
-          v[j + 1] = w[1];
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < kVals; ++j) v[j] = (col_ok && k0 + j < n) ? src[j] : 0.0;
-      }
-    } else {
-      const double* src = X + (col_ok ? cc_p : 0) + slab + na * (int64_t)k0;
-#pragma unroll
-      for (int j = 0; j < kVals; ++j) {
-        v[j] = (col_ok && k0 + j < n) ? *src : 0.0;
-        src += na;
-      }
-    }
+  // column of this lane in group q of the run (validity, global fibre index)
+  auto column = [&](int q, int64_t& ca, int64_t& fib) {
+    const int64_t grp = grp0 + q;
+    const int64_t ct = MODE1 ? grp : grp % jb.tiles_a;
+    const int64_t bslab = MODE1 ? 0 : grp / jb.tiles_a;
+    ca = ct * kGroupCols + kWaveCols * wave + l;
+    fib = MODE1 ? ca : ca + na * bslab;
   };
-  // writes the digit planes of v to LDS (column pc, chunk offset kVals ps)
-  auto split_vals = [&](const double (&v)[kVals], int E) {
-    const bool ok = E != kBadExp;
-    uint8_t* dst = lds + pc * kLdsRow + kVals * ps;
+  // item -> (group of the run, term, chunk)
+  auto decode = [&](int i, int& q, int& tm, int& ci) {
+    ci = i % nch;
+    tm = (i / nch) % nterms;
+    q = i / (nch * nterms);
+  };
+  // tensor digits of item i, k-step k: this lane's 64 bytes
+  auto bptr = [&](int i, int k64) {
+    int q, tm, ci;
+    decode(i, q, tm, ci);
+    int64_t ca, fib;
+    column(q, ca, fib);
+    const uint8_t* D = (const uint8_t*)jb.X[tm];
+    return D + (ca < nfib ? fib : 0) * rowbytes + 64 * g + 4 * ((int64_t)ci * kPanelK + k64);
+  };
+  // panel of item i: thread tid holds 16-byte unit `lane` of rows wave + 8 r
+  v4i pn[8];
+  int pen = 0;
+  auto fetch_panel = [&](int i) {
+    int q, tm, ci;
+    decode(i, q, tm, ci);
+    const uint8_t* P = (const uint8_t*)jb.P[tm];
+    const int kc = ci * kPanelK;
+    const int units = (ldp - kc < kPanelK ? ldp - kc : kPanelK) / 4;
 #pragma unroll
-    for (int j = 0; j < kVals; j += 4) {
-      uint32_t w[4], d[4];
+    for (int r = 0; r < 8; ++r)
+      pn[r] = lane < units ? *(const v4i*)(P + (int64_t)(row0 + wave + 8 * r) * rowbytes + 4 * kc + 16 * lane)
+                           : v4i{0, 0, 0, 0};
+    if (tid < kPanelRows) pen = ((const int*)(P + rowbytes * ldp))[row0 + tid];
+  };
+  auto store_panel = [&](int buf) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = ok ? digit_word(v[j + q], E) : 0u;
-      digit_planes(w[0], w[1], w[2], w[3], d);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) *(uint32_t*)(dst + k * kCols * kLdsRow + j) = d[k];
-    }
+    for (int r = 0; r < 8; ++r) *(v4i*)(panel[buf] + (wave + 8 * r) * kPanelRow + 16 * lane) = pn[r];
+    if (tid < kPanelRows) pexp[buf][tid] = pen;
+  };
+  auto same_panel = [&](int i, int j) {   // items i and j use one panel (always, without SWAP)
+    return !SWAP || (i % (nch * nterms)) == (j % (nch * nterms));
   };
 
-  double out[kTM][2][4];
+  fetch_panel(0);
+  store_panel(0);
+  int pb = 0;
+  v4i bA[4], bB[4];
+  {
+    const uint8_t* p = bptr(0, 0);
 #pragma unroll
-  for (int m = 0; m < kTM; ++m)
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) out[m][u][r] = 0.0;
-
-  for (int term = 0; term < jb.nterms; ++term) {
-    const double* __restrict__ X = (const double*)jb.X[term];
-    const uint8_t* __restrict__ P = (const uint8_t*)jb.P[term];
-    const int* __restrict__ Pexp = (const int*)(P + 4 * plane);   // after the ldp rows of 4 ldp bytes
-    const double sc = jb.scale[term];
-    const bool one_chunk = n <= kChunk;
-
-    // phase 1: exponent of every column (a one-chunk contraction keeps its
-    // values in LDS for phase 2)
-    double* myraw = raw + tid * kRawRow;
-    __syncthreads();   // the previous term's readers of colexp / lds / raw are done
-    {
-      double m = 0.0, z = 0.0;   // z = sum of 0 * v: NaN iff some value is not finite
-      for (int kc = 0; kc < n; kc += kChunk) {
-        double v[kVals];
-        load_vals(X, kc, v);
-#pragma unroll
-        for (int j = 0; j < kVals; ++j) {
-          z = fma(0.0, v[j], z);
-          m = fmax(m, fabs(v[j]));
-        }
-        if (one_chunk) {
-#pragma unroll
-          for (int j = 0; j < kVals; j += 2) *(d2*)(myraw + j) = d2{v[j], v[j + 1]};
-        }
-      }
-      red[ps][pc] = z != z ? __builtin_inf() : m;
-    }
-    __syncthreads();
-    if (tid < kCols) {
-      double m = red[0][tid];
-      for (int q = 1; q < kParts; ++q) m = fmax(m, red[q][tid]);
-      colexp[tid] = isfinite(m) ? exp_above(m) : kBadExp;
-    }
-
-    v4i acc[5][kTM][2];   // [order a + b - 2][row block][column block]
-#pragma unroll
-    for (int o = 0; o < 5; ++o)
-#pragma unroll
-      for (int m = 0; m < kTM; ++m)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) acc[o][m][u] = v4i{0, 0, 0, 0};
-
-    for (int kc = 0; kc < n; kc += kChunk) {
-      __syncthreads();   // colexp written; the previous chunk's readers are done
-      // phase 2: digit planes of this chunk
-      {
-        double v[kVals];
-        if (one_chunk) {
-#pragma unroll
-          for (int j = 0; j < kVals; j += 2) {
-            const d2 w = *(const d2*)(myraw + j);
-            v[j] = w[0];
-            v[j + 1] = w[1];
-          }
-        } else {
-          load_vals(X, kc, v);
-        }
-        split_vals(v, colexp[pc]);
-      }
-      __syncthreads();
-      // phase 3: this wave's rows against the 32 columns, 64 k per step; the
-      // next step's matrix digits load while this step's products run
-      if (active) {
-        const uint8_t* prow = P + (int64_t)(wrow + l) * 4 * ldp + (kc / 16 + g) * 64;
-        const int64_t mstride = (int64_t)16 * 4 * ldp;
-        const int kend = n - kc < kChunk ? n - kc : kChunk;
-        auto load_a = [&](int k64, v4i (&a)[kTM][4]) {
-#pragma unroll
-          for (int m = 0; m < kTM; ++m) {
-            const uint8_t* q = prow + m * mstride + 4 * k64;
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) a[m][s2] = *(const v4i*)(q + 16 * s2);
-          }
-        };
-        v4i acur[kTM][4], anext[kTM][4];
-        load_a(0, acur);
-#pragma unroll
-        for (int k64 = 0; k64 < kChunk; k64 += 64) {
-          if (k64 >= kend) break;
-          if (k64 + 64 < kend) load_a(k64 + 64, anext);
-          v4i b[2][4];
-#pragma unroll
-          for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-              b[u][s2] = *(const v4i*)(lds + (s2 * kCols + 16 * u + l) * kLdsRow + k64 + 16 * g);
-#pragma unroll
-          for (int m = 0; m < kTM; ++m)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-              const v4i* a = acur[m];
-              // matrix digit pb (first operand), tensor digit pa, order pa + pb >= 2
-              acc[4][m][u] = mfma_i8(a[3], b[u][3], acc[4][m][u]);
-              acc[3][m][u] = mfma_i8(a[3], b[u][2], acc[3][m][u]);
-              acc[3][m][u] = mfma_i8(a[2], b[u][3], acc[3][m][u]);
-              acc[2][m][u] = mfma_i8(a[3], b[u][1], acc[2][m][u]);
-              acc[2][m][u] = mfma_i8(a[2], b[u][2], acc[2][m][u]);
-              acc[2][m][u] = mfma_i8(a[1], b[u][3], acc[2][m][u]);
-              acc[1][m][u] = mfma_i8(a[3], b[u][0], acc[1][m][u]);
-              acc[1][m][u] = mfma_i8(a[2], b[u][1], acc[1][m][u]);
-              acc[1][m][u] = mfma_i8(a[1], b[u][2], acc[1][m][u]);
-              acc[1][m][u] = mfma_i8(a[0], b[u][3], acc[1][m][u]);
-              acc[0][m][u] = mfma_i8(a[2], b[u][0], acc[0][m][u]);
-              acc[0][m][u] = mfma_i8(a[1], b[u][1], acc[0][m][u]);
-              acc[0][m][u] = mfma_i8(a[0], b[u][2], acc[0][m][u]);
-            }
-          if (k64 + 64 < kend) {
-#pragma unroll
-            for (int m = 0; m < kTM; ++m)
-#pragma unroll
-              for (int s2 = 0; s2 < 4; ++s2) acur[m][s2] = anext[m][s2];
-          }
-        }
-      }
-    }
-    // this term's products:
-    // 2^(Ex + Ep - 12) (acc6 + acc5 2^-8 + acc4 2^-16 + acc3 2^-24 + acc2 2^-32)
-    if (active) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int ex = colexp[16 * u + l];
-#pragma unroll
-        for (int m = 0; m < kTM; ++m)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ep = Pexp[wrow + 16 * m + 4 * g + r];
-            double w = (double)acc[0][m][u][r] * 0x1p-32;
-            w = fma((double)acc[1][m][u][r], 0x1p-24, w);
-            w = fma((double)acc[2][m][u][r], 0x1p-16, w);
-            w = fma((double)acc[3][m][u][r], 0x1p-8, w);
-            w += (double)acc[4][m][u][r];
-            w = (ex == kBadExp || ep == kBadExp) ? __builtin_nan("") : ldexp(w, ex + ep - 12);
-            out[m][u][r] = fma(sc, w, out[m][u][r]);
-          }
-      }
-    }
+    for (int sp = 0; sp < 4; ++sp) bA[sp] = *(const v4i*)(p + 16 * sp);
   }
-  if (!active) return;   // no barrier follows
-  double* __restrict__ Y = (double*)jb.Y;
-  const double* __restrict__ base = (const double*)jb.base;
+  __syncthreads();
+
+  double out[4][4];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int64_t cc = c0 + 16 * u + l;
-    if (cc >= ncols) continue;
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int m = 0; m < kTM; ++m)
+    for (int r = 0; r < 4; ++r) out[m][r] = 0.0;
+  v4i acc[5][4];   // [order a + b - 2][row block]
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = wrow + 16 * m + 4 * g + r;
-        if (i >= n) continue;
-        const int64_t o = MODE1 ? i + (int64_t)n * cc : cc + na * (int64_t)i + slab;
-        Y[o] = base ? base[o] + out[m][u][r] : out[m][u][r];
+  for (int o = 0; o < 5; ++o)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[o][m] = v4i{0, 0, 0, 0};
+
+  // state of the current item
+  int i = 0, q = 0, tm = 0, ci = 0, kend = 0, ex = 0;
+  int64_t ca = 0, fib = 0;
+  const uint8_t* bcur = nullptr;
+  const uint8_t* bnext = nullptr;
+  auto begin_item = [&]() {
+    decode(i, q, tm, ci);
+    column(q, ca, fib);
+    const int kc = ci * kPanelK;
+    const int kw = ldp - kc < kPanelK ? ldp - kc : kPanelK;
+    kend = n - kc < kw ? n - kc : kw;
+    // unconditional (clamped) for the same reason as the digit loads below
+    ex = ((const int*)((const uint8_t*)jb.X[tm] + ntot * rowbytes))[ca < nfib ? fib : 0];
+    bcur = bptr(i, 0);
+    bnext = i + 1 < nitems ? bptr(i + 1, 0) : bcur;   // after the last item: a harmless reload
+  };
+  auto end_item = [&]() {
+    if (ci == nch - 1) {
+      // 2^(Ex + Ep - 12) (acc6 + acc5 2^-8 + acc4 2^-16 + acc3 2^-24 + acc2 2^-32)
+      const double sc = jb.scale[tm];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ep = pexp[pb][16 * m + 4 * g + r];
+          double w = (double)acc[0][m][r] * 0x1p-32;
+          w = fma((double)acc[1][m][r], 0x1p-24, w);
+          w = fma((double)acc[2][m][r], 0x1p-16, w);
+          w = fma((double)acc[3][m][r], 0x1p-8, w);
+          w += (double)acc[4][m][r];
+          w = (ex == kBadExp || ep == kBadExp) ? __builtin_nan("") : ldexp(w, ex + ep - 12);
+          out[m][r] = fma(sc, w, out[m][r]);
+          if (SWAP) __builtin_amdgcn_sched_barrier(0);   // one output at a time (registers)
+        }
+#pragma unroll
+      for (int o = 0; o < 5; ++o)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[o][m] = v4i{0, 0, 0, 0};
+      if (tm == nterms - 1) {   // the group's outputs are complete
+        if (ca < nfib) {
+          double* __restrict__ Y = (double*)jb.Y;
+          const double* __restrict__ base = (const double*)jb.base;
+          const int64_t slab = MODE1 ? 0 : na * (int64_t)n * ((grp0 + q) / jb.tiles_a);
+          auto off = [&](int ii) { return MODE1 ? ii + (int64_t)n * ca : ca + na * (int64_t)ii + slab; };
+          if (base) {   // base values in flight eight at a time (rows past n read row n - 1)
+#pragma unroll
+            for (int m0 = 0; m0 < 4; m0 += 2) {
+              double bv[2][4];
+#pragma unroll
+              for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int ii = row0 + 16 * (m0 + m) + 4 * g + r;
+                  bv[m][r] = base[off(ii < n ? ii : n - 1)];
+                }
+#pragma unroll
+              for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) out[m0 + m][r] = bv[m][r] + out[m0 + m][r];
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int i0 = row0 + 16 * m + 4 * g;
+            if (MODE1 && (n % 2) == 0 && i0 + 4 <= n) {   // 16-byte aligned runs of 4 rows
+              *(d2*)(Y + off(i0)) = d2{out[m][0], out[m][1]};
+              *(d2*)(Y + off(i0) + 2) = d2{out[m][2], out[m][3]};
+              continue;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (i0 + r < n) Y[off(i0 + r)] = out[m][r];
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) out[m][r] = 0.0;
       }
+    }
+    if (i + 1 < nitems && !same_panel(i, i + 1)) {
+      // every wave is past its reads of panel[pb ^ 1] (an earlier item's)
+      fetch_panel(i + 1);
+      store_panel(pb ^ 1);
+      __syncthreads();
+      pb ^= 1;
+    }
+  };
+  // one k-step: the next step's digits (this item's or the next item's first)
+  // are requested into `nxt` before the products of `cur` are issued
+  auto kstep = [&](int k64, v4i (&cur)[4], v4i (&nxt)[4]) {
+    // unconditional, so that the wait before the products counts only the
+    // loads of `cur` (a branch here makes the compiler wait for all loads)
+    const uint8_t* pnx = k64 + 64 < kend ? bcur + 4 * (k64 + 64) : bnext;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) nxt[sp] = *(const v4i*)(pnx + 16 * sp);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint8_t* pcur = panel[pb];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const uint8_t* pa = pcur + (16 * m + l) * kPanelRow + 4 * k64 + 64 * g;
+      v4i a[4];
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) a[sp] = *(const v4i*)(pa + 16 * sp);
+      // matrix digit (first operand), tensor digit (second), order >= 2
+      acc[4][m] = mfma_i8(a[3], cur[3], acc[4][m]);
+      acc[3][m] = mfma_i8(a[3], cur[2], acc[3][m]);
+      acc[3][m] = mfma_i8(a[2], cur[3], acc[3][m]);
+      acc[2][m] = mfma_i8(a[3], cur[1], acc[2][m]);
+      acc[2][m] = mfma_i8(a[2], cur[2], acc[2][m]);
+      acc[2][m] = mfma_i8(a[1], cur[3], acc[2][m]);
+      acc[1][m] = mfma_i8(a[3], cur[0], acc[1][m]);
+      acc[1][m] = mfma_i8(a[2], cur[1], acc[1][m]);
+      acc[1][m] = mfma_i8(a[1], cur[2], acc[1][m]);
+      acc[1][m] = mfma_i8(a[0], cur[3], acc[1][m]);
+      acc[0][m] = mfma_i8(a[2], cur[0], acc[0][m]);
+      acc[0][m] = mfma_i8(a[1], cur[1], acc[0][m]);
+      acc[0][m] = mfma_i8(a[0], cur[2], acc[0][m]);
+      if (SWAP) __builtin_amdgcn_sched_barrier(0);   // one row block's operands at a time (registers)
+    }
+  };
+  begin_item();
+  for (;;) {
+    // pairs of steps with the two digit buffers trading roles (a register
+    // copy of a buffer would wait on its load in flight)
+    int k = 0;
+    for (; k + 64 < kend; k += 128) {
+      kstep(k, bA, bB);
+      kstep(k + 64, bB, bA);
+    }
+    const bool odd = k < kend;
+    if (odd) kstep(k, bA, bB);   // the next item's first digits land in bB
+    end_item();
+    if (++i == nitems) break;
+    begin_item();
+    if (odd) {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) bA[sp] = bB[sp];
+    }
   }
 }
 
@@ -386,6 +502,11 @@ size_t packed_bytes_i8(int n) {
   return 4 * ldp * ldp + 4 * ldp;
 }
 
+size_t i8_digit_bytes(int64_t N, int n) {
+  const int64_t fibres = N / n;
+  return (size_t)round_up(fibres * (4 * (int64_t)packed_ld(n) + 4), 256);
+}
+
 int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t s) {
   const int ldp = packed_ld(n);
   hipLaunchKernelGGL(pack_i8_kernel, dim3((unsigned)ldp), dim3(256), 0, s, M, n, ldp, scale, (uint8_t*)out);
@@ -393,29 +514,91 @@ int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t 
   return SETD_OK;
 }
 
-int launch_mode_i8(ModeJobs& J, bool mode1, hipStream_t s) {
-  int64_t tot = 0;
+int launch_mode_i8(ModeJobs& J, bool mode1, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (J.njobs == 0) return SETD_OK;
+  // 1. one digit buffer per distinct input tensor of the launch
+  const void* inputs[kMaxJobs * kMaxTerms];
+  int ninputs = 0;
+  int slot_of[kMaxJobs][kMaxTerms];
+  size_t per = 0;
   for (int j = 0; j < J.njobs; ++j) {
-    ModeJob& jb = J.job[j];
-    jb.tiles_i = (int)ceil_div(jb.n, kRows);
-    jb.tiles_a = (int)ceil_div(mode1 ? jb.nb : jb.na, kCols);
-    jb.tile_begin = tot;
-    tot += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
+    const ModeJob& jb = J.job[j];
+    per = std::max(per, i8_digit_bytes(jb.na * jb.n * jb.nb, jb.n));
+    for (int t = 0; t < jb.nterms; ++t) {
+      int k = 0;
+      while (k < ninputs && inputs[k] != jb.X[t]) ++k;
+      if (k == ninputs) inputs[ninputs++] = jb.X[t];
+      slot_of[j][t] = k;
+    }
   }
-  J.total_tiles = tot;
-  J.tiles_per_job = J.njobs > 0 ? tot / J.njobs : 0;
-  for (int j = 0; j < J.njobs; ++j)
-    if (J.job[j].tile_begin != (int64_t)j * J.tiles_per_job) J.tiles_per_job = 0;
+  if (ws == nullptr || (size_t)ninputs * per > ws_bytes) {
+    set_error("int8 slicing workspace too small: %zu < %zu bytes", ws_bytes, (size_t)ninputs * per);
+    return SETD_EINVAL;
+  }
+  // 2. slicing launches: one job per distinct input (all jobs of a launch
+  // share the regime; inputs shared by several jobs have equal shapes)
+  for (int k0 = 0; k0 < ninputs; k0 += kMaxJobs) {
+    ModeJobs S;
+    S.njobs = 0;
+    int64_t tot = 0;
+    for (int k = k0; k < std::min(ninputs, k0 + kMaxJobs); ++k) {
+      int jj = 0, tt = 0;
+      for (int j = 0; j < J.njobs; ++j)
+        for (int t = 0; t < J.job[j].nterms; ++t)
+          if (slot_of[j][t] == k) jj = j, tt = t;
+      ModeJob sj = J.job[jj];
+      sj.nterms = 1;
+      sj.X[0] = J.job[jj].X[tt];
+      sj.Y = (char*)ws + (size_t)k * per;
+      sj.base = nullptr;
+      sj.tiles_i = 1;
+      sj.tiles_a = (int)ceil_div(mode1 ? sj.nb : sj.na, kSliceCols);
+      sj.tile_begin = tot;
+      tot += (int64_t)sj.tiles_a * (mode1 ? 1 : sj.nb);
+      S.job[S.njobs++] = sj;
+    }
+    S.total_tiles = tot;
+    S.tiles_per_job = 0;
+    const int64_t pxcd = ceil_div(tot, 8);
+    if (mode1)
+      hipLaunchKernelGGL(slice_i8_kernel<true>, dim3((unsigned)(pxcd * 8)), dim3(256), 0, s, S, pxcd);
+    else
+      hipLaunchKernelGGL(slice_i8_kernel<false>, dim3((unsigned)(pxcd * 8)), dim3(256), 0, s, S, pxcd);
+    SETD_LAUNCHED();
+  }
+  // 3. the digit GEMM: runs of `sup` column groups per workgroup, sized for
+  // about kGemmWgPerCu workgroups per compute unit over the launch
+  ModeJobs G = J;
+  int64_t pairs = 0;
+  for (int j = 0; j < G.njobs; ++j) {
+    ModeJob& jb = G.job[j];
+    jb.tiles_i = (int)ceil_div(jb.n, kPanelRows);
+    jb.tiles_a = (int)ceil_div(mode1 ? jb.nb : jb.na, kGroupCols);
+    pairs += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
+  }
+  const int sup = (int)std::min<int64_t>(kMaxSup, std::max<int64_t>(1, pairs / (kCus * kGemmWgPerCu)));
+  int64_t tot = 0;
+  for (int j = 0; j < G.njobs; ++j) {
+    ModeJob& jb = G.job[j];
+    for (int t = 0; t < jb.nterms; ++t) jb.X[t] = (char*)ws + (size_t)slot_of[j][t] * per;
+    jb.tile_begin = tot;
+    tot += (int64_t)jb.tiles_i * ceil_div((int64_t)jb.tiles_a * (mode1 ? 1 : jb.nb), sup);
+  }
+  G.total_tiles = tot;
+  G.tiles_per_job = G.njobs > 0 ? tot / G.njobs : 0;
+  for (int j = 0; j < G.njobs; ++j)
+    if (G.job[j].tile_begin != (int64_t)j * G.tiles_per_job) G.tiles_per_job = 0;
   if (tot == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
   if (prof_on()) job_work(J, 8, 8, 4, fl, by);
   ProfScope prof(s, mode1 ? kProfMode1LP : kProfModeBLP, fl, by);
-  const int64_t per = ceil_div(tot, 8);
-  const dim3 grid((unsigned)(per * 8));
-  if (mode1)
-    hipLaunchKernelGGL(mode_i8_kernel<true>, grid, dim3(kThreads), 0, s, J, per);
-  else
-    hipLaunchKernelGGL(mode_i8_kernel<false>, grid, dim3(kThreads), 0, s, J, per);
+  bool swap = false;
+  for (int j = 0; j < G.njobs; ++j) swap = swap || G.job[j].nterms > 1 || G.job[j].n > kPanelK;
+  const int64_t pxcd = ceil_div(tot, 8);
+  const dim3 grid((unsigned)(pxcd * 8));
+  auto kern = mode1 ? (swap ? gemm_i8_kernel<true, true> : gemm_i8_kernel<true, false>)
+                    : (swap ? gemm_i8_kernel<false, true> : gemm_i8_kernel<false, false>);
+  hipLaunchKernelGGL(kern, grid, dim3(512), 0, s, G, pxcd, sup);
   SETD_LAUNCHED();
   return SETD_OK;
 }

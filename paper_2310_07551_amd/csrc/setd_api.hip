@@ -108,11 +108,13 @@ struct LaunchKind {
   bool mode1;
   int prec;
   DType out;
+  void* i8ws = nullptr;      // digit buffers (SETD_PREC_I8X4)
+  size_t i8bytes = 0;
 };
 
 int launch_jobs(ModeJobs& J, const LaunchKind& k, hipStream_t s) {
   if (k.prec == SETD_PREC_F64) return k.mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
-  if (k.prec == SETD_PREC_I8X4) return launch_mode_i8(J, k.mode1, s);
+  if (k.prec == SETD_PREC_I8X4) return launch_mode_i8(J, k.mode1, k.i8ws, k.i8bytes, s);
   return k.mode1 ? launch_mode1_lp(J, k.prec, k.out, s) : launch_modeB_lp(J, k.prec, k.out, s);
 }
 
@@ -162,11 +164,21 @@ int setd::launch_f64_jobs(std::vector<ModeJob>& jobs, bool mode1, hipStream_t s)
   return SETD_OK;
 }
 
-int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s) {
+size_t setd::i8_slot_bytes(int d, const int* dims) {
+  int64_t N = 1;
+  for (int mu = 0; mu < d; ++mu) N *= dims[mu];
+  size_t b = 0;
+  for (int mu = 0; mu < d; ++mu) b = std::max(b, i8_digit_bytes(N, dims[mu]));
+  return b;
+}
+
+int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s,
+                           void* i8ws, size_t i8bytes) {
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) N *= dims[mu];
   const DType mid = fp32_storage(prec) ? DType::F32 : DType::F64;
-  const LaunchKind k1{true, prec, mid}, kb{false, prec, mid}, klast{false, prec, DType::F64};
+  const LaunchKind k1{true, prec, mid, i8ws, i8bytes}, kb{false, prec, mid, i8ws, i8bytes},
+      klast{false, prec, DType::F64, i8ws, i8bytes};
   ModeJobs J;
   J.njobs = 0;
   // mode 1 -> Y1
@@ -400,7 +412,7 @@ int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, co
                        c->Y2[cc][k * T + t]};
       }
     }
-    SETD_TRY(run_tucker_group(d, c->dims, outs, no, prec, s));
+    SETD_TRY(run_tucker_group(d, c->dims, outs, no, prec, s, c->i8_mem.p, c->i8_mem.bytes));
   }
   // 3. D2 = g(U2) - G
   SETD_TRY(launch_stage_d(b.U2, b.G, nc, N, gp, b.D2, tdt, s));
@@ -415,7 +427,7 @@ int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, co
       for (int t = 0; t < T; ++t)
         o.term[t] = {D2c_(cc), c->bank[cc][e32][t], 4.0 * tau / 3.0 * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
-    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s));
+    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s, c->i8_mem.p, c->i8_mem.bytes));
   }
   // 5. D3 = g(U3) - G
   SETD_TRY(launch_stage_d(b.U3, b.G, nc, N, gp, b.D3, tdt, s));
@@ -430,7 +442,7 @@ int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, co
       for (int t = 0; t < T; ++t)
         o.term[t] = {D3c_(cc), c->bank[cc][ef2][t], 1.5 * tau * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
-    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s));
+    SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s, c->i8_mem.p, c->i8_mem.bytes));
   }
   return SETD_OK;
 }
@@ -460,7 +472,7 @@ int step2_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
     o.nterms = 1;
     o.term[0] = {(char*)c->F + cc * N * es, c->bank2[cc][0], c->tau, c->Y1[cc][0], c->Y2[cc][0]};
   }
-  SETD_TRY(run_tucker_group(d, c->dims, outs, nc, c->prec, s));
+  SETD_TRY(run_tucker_group(d, c->dims, outs, nc, c->prec, s, c->i8_mem.p, c->i8_mem.bytes));
   SETD_TRY(launch_stage_d(c->U2, c->G, nc, N, gp, c->D, tdt, s));
   const double fact = std::ldexp(1.0, d - 1);   // 2!^{d-1}
   for (int cc = 0; cc < nc; ++cc) {
@@ -470,7 +482,7 @@ int step2_once(setd_ctx* c, double* u, const GParams& gp, hipStream_t s) {
     o.nterms = 1;
     o.term[0] = {(char*)c->D + cc * N * es, c->bank2[cc][1], c->tau * fact, c->Y1[cc][0], c->Y2[cc][0]};
   }
-  return run_tucker_group(d, c->dims, outs, nc, c->prec, s);
+  return run_tucker_group(d, c->dims, outs, nc, c->prec, s, c->i8_mem.p, c->i8_mem.bytes);
 }
 
 typedef int (*StepFn)(setd_ctx*, double*, const GParams&, hipStream_t);
@@ -687,8 +699,12 @@ size_t setd_tucker_workspace_bytes(int d, const int64_t* dims, int prec) {
   }
   if (!is_prec(prec)) return 0;
   // two ping-pong intermediates, plus the FP32 copy of V for reduced precision
+  // or one int8 digit buffer for the error-free slicing form
   const int nbuf = fp32_storage(prec) ? 3 : 2;
-  return pk + nbuf * round_up(N * (int64_t)sizeof(double), 256) + 256;
+  size_t dig = 0;
+  if (prec == SETD_PREC_I8X4)
+    for (int mu = 0; mu < d; ++mu) dig = std::max(dig, i8_digit_bytes(N, (int)dims[mu]));
+  return pk + nbuf * round_up(N * (int64_t)sizeof(double), 256) + dig + 256;
 }
 
 int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, const double* const* M, double alpha,
@@ -746,6 +762,13 @@ int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, co
   q += (lp ? 3 : 2) * fb;
   void* P[8] = {};
   int rc = SETD_OK;
+  for (int k = 0; k < nm; ++k) q += round_up(packed_bytes((int)dims[modes[k]], prec), 256);
+  // the int8 digit buffer (SETD_PREC_I8X4) follows the packed matrices
+  void* dig = q;
+  size_t dig_bytes = 0;
+  if (prec == SETD_PREC_I8X4)
+    for (int mu = 0; mu < d; ++mu) dig_bytes = std::max(dig_bytes, i8_digit_bytes(N, (int)dims[mu]));
+  q = (char*)round_up((int64_t)(uintptr_t)wsp, 256) + (lp ? 3 : 2) * fb;
   for (int k = 0; k < nm && rc == SETD_OK; ++k) {
     const int mu = modes[k];
     P[mu] = q;
@@ -769,7 +792,7 @@ int setd_tucker_apply(const double* V, double* W, int d, const int64_t* dims, co
     ModeJobs J;
     J.njobs = 1;
     J.job[0] = mk_job(src, P[mu], 1.0, dst, last ? base : nullptr, na, (int)dims[mu], nb);
-    const LaunchKind kind{mu == 0, prec, (last || !lp) ? DType::F64 : DType::F32};
+    const LaunchKind kind{mu == 0, prec, (last || !lp) ? DType::F64 : DType::F32, dig, dig_bytes};
     rc = launch_jobs(J, kind, s);
     src = dst;
   }
@@ -907,6 +930,12 @@ int setd_ctx_create(setd_ctx** out, int d, const int64_t* dims, int ncomp, const
       }
     c->aux = take(1);
   }
+  // int8 digit buffers: one per input of the largest launch (the phi_1 group:
+  // 3 stages x nterms x ncomp)
+  if (c->prec == SETD_PREC_I8X4) {
+    const size_t slot = i8_slot_bytes(d, c->dims);
+    if ((rc = c->i8_mem.alloc((size_t)3 * c->nterms * ncomp * slot)) != SETD_OK) return fail(rc);
+  }
   if ((rc = build_bank(c, s)) != SETD_OK) return fail(rc);
   *out = c;
   return SETD_OK;
@@ -953,7 +982,7 @@ int setd_split_phi_apply(setd_ctx* c, int comp, int ell, int stage, const double
   o.nterms = S.nterms;
   for (int t = 0; t < S.nterms; ++t)
     o.term[t] = {src, c->bank[comp][e][t], scale * S.eta[t], c->Y1[0][t], c->Y2[0][t]};
-  return run_tucker_group(c->d, c->dims, &o, 1, c->prec, s);
+  return run_tucker_group(c->d, c->dims, &o, 1, c->prec, s, c->i8_mem.p, c->i8_mem.bytes);
 }
 
 int setd_etd_step(setd_ctx* c, double* u, int nsteps, double tau, int g_kind, const double* params, int nparams,
