@@ -198,7 +198,11 @@ size_t packed_bytes(int n, int prec);
 size_t packed_bytes_i8(int n);
 int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t s);
 size_t i8_digit_bytes(int64_t N, int n);
-int launch_mode_i8(ModeJobs& jobs, bool mode1, void* ws, size_t ws_bytes, hipStream_t s);
+// presliced: the jobs' X[t] are already digit buffers (no slicing pass).
+// fuse_next = n2 in {128, 256} (mode 1 only): the jobs' Y receive the digit
+// buffer of the mode-2 operand instead of the FP64 product.
+int launch_mode_i8(ModeJobs& jobs, bool mode1, void* ws, size_t ws_bytes, hipStream_t s, bool presliced = false,
+                   int fuse_next = 0);
 
 // Pointwise helpers (pointwise.hip).
 int launch_axpby(const double* x, double* y, int64_t n, double a, double b, hipStream_t s);  // y = a x + b y

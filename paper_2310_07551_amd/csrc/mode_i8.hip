@@ -40,6 +40,7 @@
 // 64-long k-step, and register r of lane (g, l) holds D[4 g + r][l].
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -55,6 +56,9 @@ constexpr int kBadExp = 1 << 14;        // marks a vector with a non-finite entr
 constexpr int kSliceCols = 32;
 constexpr int kSliceChunk = 256;
 constexpr int kStageRow = 4 * kSliceChunk + 16;   // LDS row of one fibre's digits, padded against bank conflicts
+// digit buffer tiles: 16 fibres x one 64-long k-step = 4 planes x 64 lanes x 16 bytes
+constexpr int kPlaneBytes = 1024;
+constexpr int kTileBytes = 4 * kPlaneBytes;
 // digit GEMM: 8 waves x (64 rows x 16 columns); the matrix panel holds 64
 // rows x 256 contraction values (4 bytes each), rows padded by 16 bytes so
 // that neighbouring lanes read different banks
@@ -64,6 +68,7 @@ constexpr int kWaveCols = 16;
 constexpr int kGroupCols = kGemmWaves * kWaveCols;   // 128 columns per workgroup
 constexpr int kPanelK = 256;
 constexpr int kPanelRow = 4 * kPanelK + 16;
+constexpr int kHbPitch = kPanelRow / 8;   // doubles per LDS row of the fused epilogue's first-group values
 #ifndef SETD_I8_WG_PER_CU
 #define SETD_I8_WG_PER_CU 12
 #endif
@@ -146,8 +151,13 @@ __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
 // ---- slicing kernel ----
 // Job j: X[0] = FP64 tensor, Y = digit buffer.  MODE1: fibre b holds
 // X[p + n b] (p contiguous); otherwise fibre c = a + na b holds
-// X[a + na p + na n b].  Fibre c's planes: D + c 4 ldp, value p's digit s at
-// (p / 16) 64 + 16 s + p % 16; then one int32 exponent per fibre.
+// X[a + na p + na n b].  The buffer is tiled the way the matrix cores read
+// it: tile (c / 16, p / 64) of kTileBytes at ((c / 16) (ldp / 64) + p / 64)
+// kTileBytes holds digit plane s at s kPlaneBytes, and there the 16 bytes of
+// lane 16 ((p / 16) % 4) + c % 16: the digits of values p / 16 16 .. + 15 of
+// fibre c.  One load instruction of a wave thus reads 1 KB of contiguous
+// memory.  After the tiles of round_up(fibres, 16) fibres: one int32
+// exponent per fibre.
 // A workgroup slices 32 fibres that are consecutive in the digit buffer, 256
 // values at a time, each thread 32 values of one fibre.  The digit planes are
 // assembled in LDS and leave as whole fibre rows (1 KB per fibre and chunk),
@@ -180,7 +190,7 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
   const int64_t fib0 = MODE1 ? fa0 : fa0 + na * bslab;
   const int64_t ntot = MODE1 ? nb : na * nb;
   uint8_t* __restrict__ D = (uint8_t*)jb.Y;
-  int* __restrict__ Dexp = (int*)(D + ntot * 4 * (int64_t)ldp);
+  int* __restrict__ Dexp = (int*)(D + ((ntot + 15) & ~(int64_t)15) * 4 * (int64_t)ldp);
   double v[32];
   auto load = [&](int kc) {
     const int k0 = kc + 32 * ps;
@@ -240,10 +250,16 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
         *(v4i*)(o + 16 * sp) = v4i{(int)d[0][sp], (int)d[1][sp], (int)d[2][sp], (int)d[3][sp]};
     }
     __syncthreads();
-    const int units = kw / 4;   // 16-byte units per fibre row of this chunk
-    for (int e = tid; e < nv * units; e += 256) {
-      const int f = e / units, u = e - f * units;
-      *(v4i*)(D + (fib0 + f) * 4 * (int64_t)ldp + 4 * kc + 16 * u) = *(const v4i*)(stage + f * kStageRow + 16 * u);
+    // 16-byte units in tile order: (local block of 16 fibres, k-step, plane, lane)
+    const int nks = ldp / 64, ksc = kw / 64;
+    for (int e = tid; e < kSliceCols * kw / 4; e += 256) {
+      const int ln = e & 63, sp = (e >> 6) & 3, rest = e >> 8;
+      const int cbl = rest / ksc, ks = rest - cbl * ksc;
+      const int pcw = 16 * cbl + (ln & 15), gg = ln >> 4;
+      if (pcw >= nv) continue;
+      const int64_t f = fib0 + pcw;
+      uint8_t* dst = D + (((f >> 4) * nks + kc / 64 + ks) * 4 + sp) * (int64_t)kPlaneBytes + 16 * (16 * gg + (f & 15));
+      *(v4i*)dst = *(const v4i*)(stage + pcw * kStageRow + 64 * (4 * ks + gg) + 16 * sp);
     }
     __syncthreads();   // the stage is rewritten by the next chunk
   }
@@ -261,10 +277,12 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
 // during the current item into the second LDS buffer (SWAP; the host picks
 // it when some job has several terms or n > 256).  Without SWAP the panel is
 // loaded once and the loop has no barrier at all.
-template <bool MODE1, bool SWAP>
-__global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64_t per_xcd, int sup) {
+template <bool MODE1, bool SWAP, bool FUSE>
+__global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64_t per_xcd, int sup, int nnext) {
   __shared__ __attribute__((aligned(16))) uint8_t panel[2][kPanelRows * kPanelRow];
   __shared__ int pexp[2][kPanelRows];
+  __shared__ int emax[FUSE ? 2 : 1][kGemmWaves][kPanelRows];   // FUSE: biased exponent maxima per half, wave, row
+  __shared__ int erow[kPanelRows];
   const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;   // uniform over the block
   const ModeJob& jb = J.job[find_job(J, t)];
@@ -283,9 +301,10 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   const int row0 = it * kPanelRows;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, l = lane & 15;
   const int64_t rowbytes = 4 * (int64_t)ldp;
+  const int64_t ntot16 = (ntot + 15) & ~(int64_t)15;   // fibres of the digit tiles
 
   // column of this lane in group q of the run (validity, global fibre index)
-  auto column = [&](int q, int64_t& ca, int64_t& fib) {
+  auto column = [&](int q, int64_t& ca, int64_t& fib) __attribute__((always_inline)) {
     const int64_t grp = grp0 + q;
     const int64_t ct = MODE1 ? grp : grp % jb.tiles_a;
     const int64_t bslab = MODE1 ? 0 : grp / jb.tiles_a;
@@ -293,24 +312,25 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     fib = MODE1 ? ca : ca + na * bslab;
   };
   // item -> (group of the run, term, chunk)
-  auto decode = [&](int i, int& q, int& tm, int& ci) {
+  auto decode = [&](int i, int& q, int& tm, int& ci) __attribute__((always_inline)) {
     ci = i % nch;
     tm = (i / nch) % nterms;
     q = i / (nch * nterms);
   };
   // tensor digits of item i, k-step k: this lane's 64 bytes
-  auto bptr = [&](int i, int k64) {
+  auto bptr = [&](int i, int k64) __attribute__((always_inline)) {
     int q, tm, ci;
     decode(i, q, tm, ci);
     int64_t ca, fib;
     column(q, ca, fib);
     const uint8_t* D = (const uint8_t*)jb.X[tm];
-    return D + (ca < nfib ? fib : 0) * rowbytes + 64 * g + 4 * ((int64_t)ci * kPanelK + k64);
+    const int64_t f = ca < nfib ? fib : 0;
+    return D + ((f >> 4) * (ldp / 64) + (ci * kPanelK + k64) / 64) * (int64_t)kTileBytes + 16 * (16 * g + (f & 15));
   };
   // panel of item i: thread tid holds 16-byte unit `lane` of rows wave + 8 r
   v4i pn[8];
   int pen = 0;
-  auto fetch_panel = [&](int i) {
+  auto fetch_panel = [&](int i) __attribute__((always_inline)) {
     int q, tm, ci;
     decode(i, q, tm, ci);
     const uint8_t* P = (const uint8_t*)jb.P[tm];
@@ -322,24 +342,18 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
                            : v4i{0, 0, 0, 0};
     if (tid < kPanelRows) pen = ((const int*)(P + rowbytes * ldp))[row0 + tid];
   };
-  auto store_panel = [&](int buf) {
+  auto store_panel = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) *(v4i*)(panel[buf] + (wave + 8 * r) * kPanelRow + 16 * lane) = pn[r];
     if (tid < kPanelRows) pexp[buf][tid] = pen;
   };
-  auto same_panel = [&](int i, int j) {   // items i and j use one panel (always, without SWAP)
+  auto same_panel = [&](int i, int j) __attribute__((always_inline)) {   // items i and j use one panel (always, without SWAP)
     return !SWAP || (i % (nch * nterms)) == (j % (nch * nterms));
   };
 
   fetch_panel(0);
   store_panel(0);
   int pb = 0;
-  v4i bA[4], bB[4];
-  {
-    const uint8_t* p = bptr(0, 0);
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp) bA[sp] = *(const v4i*)(p + 16 * sp);
-  }
   __syncthreads();
 
   double out[4][4];
@@ -358,18 +372,118 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   int64_t ca = 0, fib = 0;
   const uint8_t* bcur = nullptr;
   const uint8_t* bnext = nullptr;
-  auto begin_item = [&]() {
+  auto begin_item = [&]() __attribute__((always_inline)) {
     decode(i, q, tm, ci);
     column(q, ca, fib);
     const int kc = ci * kPanelK;
     const int kw = ldp - kc < kPanelK ? ldp - kc : kPanelK;
     kend = n - kc < kw ? n - kc : kw;
     // unconditional (clamped) for the same reason as the digit loads below
-    ex = ((const int*)((const uint8_t*)jb.X[tm] + ntot * rowbytes))[ca < nfib ? fib : 0];
+    ex = ((const int*)((const uint8_t*)jb.X[tm] + ntot16 * rowbytes))[ca < nfib ? fib : 0];
     bcur = bptr(i, 0);
     bnext = i + 1 < nitems ? bptr(i + 1, 0) : bcur;   // after the last item: a harmless reload
   };
-  auto end_item = [&]() {
+  // FUSE (mode 1 only, the next mode's n2 = nnext in {128, 256}): instead of
+  // the FP64 product, the digit planes of the next mode's operand.  Column b
+  // of this product is (i2, i3) = (b % n2, b / n2), so the nnext / 128
+  // consecutive groups of a run that share i3 hold, for each of the 64 rows
+  // i1, the whole mode-2 fibre c2 = i1 + n i3.  The first group's values wait
+  // in LDS (the second panel buffer, unused without SWAP); at the last group
+  // the fibre exponents (the maximum over both groups of the frexp exponent
+  // of every value, reduced across lanes as packed 16-bit fields: zero -> 0,
+  // non-finite -> the largest) are formed and every value is cut into its
+  // digits exactly as the slicing kernel would, a quad of lanes trading bytes
+  // so that each lane stores one 4-byte run of one plane.
+  auto fused_digits = [&](int q) __attribute__((always_inline)) {
+    if constexpr (FUSE) {
+      const int g2 = nnext / kGroupCols;
+      const int64_t grp = grp0 + q;
+      const int half = (int)(grp % g2);
+      const int64_t i3 = grp / g2;
+      double* hb = (double*)panel[1];   // [64 rows][kHbPitch] first-group values
+      typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+      us2 pk[8];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double v = out[m][r];
+          int e = 0;
+          (void)frexp(v, &e);
+          const unsigned short be = v == 0.0 ? 0 : (isfinite(v) ? (unsigned short)(e + 2048) : (unsigned short)0xFFFF);
+          pk[2 * m + (r >> 1)][r & 1] = be;
+        }
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          union { us2 v; int i; } a, b;
+          a.v = pk[k];
+          b.i = __shfl_xor(a.i, o, 64);
+          pk[k] = __builtin_elementwise_max(a.v, b.v);
+        }
+      if (l == 0)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) emax[half][wave][16 * m + 4 * g + r] = pk[2 * m + (r >> 1)][r & 1];
+      if (half != g2 - 1) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) hb[(16 * m + 4 * g + r) * kHbPitch + kWaveCols * wave + l] = out[m][r];
+        return;
+      }
+      __syncthreads();
+      const int64_t ntot2 = (int64_t)n * (nb / nnext);   // fibres of the next mode
+      const int ldp2 = nnext, nks2 = nnext / 64;
+      uint8_t* __restrict__ Dn = (uint8_t*)jb.Y;
+      if (tid < kPanelRows) {
+        int bmax = 0;
+        for (int h = 0; h < g2; ++h)
+          for (int w = 0; w < kGemmWaves; ++w) bmax = max(bmax, emax[h][w][tid]);
+        const int E = bmax == 0 ? 0 : (bmax == 0xFFFF ? kBadExp : bmax - 2048);
+        erow[tid] = E;
+        if (row0 + tid < n) {
+          const int64_t c2 = row0 + tid + (int64_t)n * i3;
+          ((int*)(Dn + ((ntot2 + 15) & ~(int64_t)15) * 4 * (int64_t)ldp2))[c2] = E;
+        }
+      }
+      __syncthreads();
+      const int t4 = l & 3;   // this lane's plane after the exchange
+      const uint32_t sel = (uint32_t)t4 | ((uint32_t)(4 + t4) << 8) | 0x0C0C0000u;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h >= g2) break;
+        const bool regs = h == g2 - 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int R = 16 * m + 4 * g + r;
+            const double v = regs ? out[m][r] : hb[R * kHbPitch + kWaveCols * wave + l];
+            const int E = erow[R];
+            const uint32_t w = E == kBadExp ? 0u : digit_word(v, E);
+            const uint32_t w0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x00, 0xF, 0xF, false);
+            const uint32_t w1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x55, 0xF, 0xF, false);
+            const uint32_t w2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0xAA, 0xF, 0xF, false);
+            const uint32_t w3 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0xFF, 0xF, 0xF, false);
+            const uint32_t x = __builtin_amdgcn_perm(w1, w0, sel);   // plane t4 of values 0, 1 of the quad
+            const uint32_t y = __builtin_amdgcn_perm(w3, w2, sel);   // of values 2, 3
+            const uint32_t d = __builtin_amdgcn_perm(y, x, 0x05040100u);
+            if (row0 + R < n) {
+              const int64_t c2 = row0 + R + (int64_t)n * i3;
+              const int i2 = kGroupCols * h + kWaveCols * wave + l;
+              uint8_t* dst = Dn + ((c2 >> 4) * nks2 + (i2 >> 6)) * (int64_t)kTileBytes + kPlaneBytes * t4 +
+                             16 * (16 * ((i2 >> 4) & 3) + (c2 & 15)) + 4 * (l >> 2);
+              *(uint32_t*)dst = d;
+            }
+          }
+      }
+      __syncthreads();   // the LDS values and exponents are rewritten by the next fibres
+    }
+  };
+  auto end_item = [&]() __attribute__((always_inline)) {
     if (ci == nch - 1) {
       // 2^(Ex + Ep - 12) (acc6 + acc5 2^-8 + acc4 2^-16 + acc3 2^-24 + acc2 2^-32)
       const double sc = jb.scale[tm];
@@ -392,11 +506,13 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
 #pragma unroll
         for (int m = 0; m < 4; ++m) acc[o][m] = v4i{0, 0, 0, 0};
       if (tm == nterms - 1) {   // the group's outputs are complete
-        if (ca < nfib) {
+        if constexpr (FUSE) {
+          fused_digits(q);
+        } else if (ca < nfib) {
           double* __restrict__ Y = (double*)jb.Y;
           const double* __restrict__ base = (const double*)jb.base;
           const int64_t slab = MODE1 ? 0 : na * (int64_t)n * ((grp0 + q) / jb.tiles_a);
-          auto off = [&](int ii) { return MODE1 ? ii + (int64_t)n * ca : ca + na * (int64_t)ii + slab; };
+          auto off = [&](int ii) __attribute__((always_inline)) { return MODE1 ? ii + (int64_t)n * ca : ca + na * (int64_t)ii + slab; };
           if (base) {   // base values in flight eight at a time (rows past n read row n - 1)
 #pragma unroll
             for (int m0 = 0; m0 < 4; m0 += 2) {
@@ -441,15 +557,11 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       pb ^= 1;
     }
   };
-  // one k-step: the next step's digits (this item's or the next item's first)
-  // are requested into `nxt` before the products of `cur` are issued
-  auto kstep = [&](int k64, v4i (&cur)[4], v4i (&nxt)[4]) {
-    // unconditional, so that the wait before the products counts only the
-    // loads of `cur` (a branch here makes the compiler wait for all loads)
-    const uint8_t* pnx = k64 + 64 < kend ? bcur + 4 * (k64 + 64) : bnext;
+  auto load4 = [&](const uint8_t* p, v4i (&dst)[4]) {
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp) nxt[sp] = *(const v4i*)(pnx + 16 * sp);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int sp = 0; sp < 4; ++sp) dst[sp] = *(const v4i*)(p + kPlaneBytes * sp);
+  };
+  auto products = [&](int k64, const v4i (&cur)[4]) {
     const uint8_t* pcur = panel[pb];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -474,25 +586,66 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       if (SWAP) __builtin_amdgcn_sched_barrier(0);   // one row block's operands at a time (registers)
     }
   };
-  begin_item();
-  for (;;) {
-    // pairs of steps with the two digit buffers trading roles (a register
-    // copy of a buffer would wait on its load in flight)
-    int k = 0;
-    for (; k + 64 < kend; k += 128) {
-      kstep(k, bA, bB);
-      kstep(k + 64, bB, bA);
-    }
-    const bool odd = k < kend;
-    if (odd) kstep(k, bA, bB);   // the next item's first digits land in bB
-    end_item();
-    if (++i == nitems) break;
+  // Digit loads are unconditional (clamped addresses), so that the wait
+  // before the products counts only the loads they consume: behind a branch
+  // the compiler waits for every load in flight.
+  //
+  // Every item of K k-steps (one term, n <= 256): K rotating buffers, the
+  // digits of step s + K - 1 (this item's or the next one's) requested at
+  // step s, so each load has K - 1 steps of products to arrive in.
+  auto run_fixed = [&](auto kc) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    v4i bb[K][4];
     begin_item();
-    if (odd) {
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) bA[sp] = bB[sp];
+    for (int s = 0; s + 1 < K; ++s) load4(bcur + kTileBytes * s, bb[s]);
+    for (;;) {
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        const int t = s + K - 1;
+        load4(t < K ? bcur + kTileBytes * t : bnext + kTileBytes * (t - K), bb[(s + K - 1) % K]);
+        __builtin_amdgcn_sched_barrier(0);   // the loads go out before the products
+        products(64 * s, bb[s]);
+      }
+      end_item();
+      if (++i == nitems) break;
+      begin_item();
     }
+  };
+  // Any items: two buffers trading roles (a register copy of a buffer would
+  // wait on its load in flight), the next step's digits requested first.
+  auto run_any = [&]() __attribute__((always_inline)) {
+    v4i bA[4], bB[4];
+    auto kstep = [&](int k64, v4i (&cur)[4], v4i (&nxt)[4]) {
+      load4(k64 + 64 < kend ? bcur + kTileBytes * ((k64 + 64) / 64) : bnext, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      products(k64, cur);
+    };
+    begin_item();
+    load4(bcur, bA);
+    for (;;) {
+      int k = 0;
+      for (; k + 64 < kend; k += 128) {
+        kstep(k, bA, bB);
+        kstep(k + 64, bB, bA);
+      }
+      const bool odd = k < kend;
+      if (odd) kstep(k, bA, bB);   // the next item's first digits land in bB
+      end_item();
+      if (++i == nitems) break;
+      begin_item();
+      if (odd) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) bA[sp] = bB[sp];
+      }
+    }
+  };
+  const int ksteps = (n + 63) / 64;
+  if constexpr (!SWAP) {
+    if (ksteps == 4) return run_fixed(std::integral_constant<int, 4>{});
+    if (ksteps == 3) return run_fixed(std::integral_constant<int, 3>{});
   }
+  run_any();
 }
 
 }  // namespace
@@ -504,7 +657,7 @@ size_t packed_bytes_i8(int n) {
 
 size_t i8_digit_bytes(int64_t N, int n) {
   const int64_t fibres = N / n;
-  return (size_t)round_up(fibres * (4 * (int64_t)packed_ld(n) + 4), 256);
+  return (size_t)round_up(round_up(fibres, (int64_t)16) * 4 * packed_ld(n) + 4 * fibres, 256);
 }
 
 int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t s) {
@@ -514,8 +667,63 @@ int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t 
   return SETD_OK;
 }
 
-int launch_mode_i8(ModeJobs& J, bool mode1, void* ws, size_t ws_bytes, hipStream_t s) {
+namespace {
+
+// The digit GEMM of a table of jobs whose X[t] are digit buffers.
+int launch_gemm_i8(const ModeJobs& J, bool mode1, hipStream_t s, int fuse_next) {
+  // runs of `sup` column groups per workgroup, sized for about kGemmWgPerCu
+  // workgroups per compute unit over the launch
+  ModeJobs G = J;
+  int64_t pairs = 0;
+  for (int j = 0; j < G.njobs; ++j) {
+    ModeJob& jb = G.job[j];
+    jb.tiles_i = (int)ceil_div(jb.n, kPanelRows);
+    jb.tiles_a = (int)ceil_div(mode1 ? jb.nb : jb.na, kGroupCols);
+    pairs += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
+  }
+  int sup = (int)std::min<int64_t>(kMaxSup, std::max<int64_t>(1, pairs / (kCus * kGemmWgPerCu)));
+  if (fuse_next == 2 * kGroupCols) sup = (sup + 1) & ~1;   // runs of whole mode-2 fibres
+  int64_t tot = 0;
+  for (int j = 0; j < G.njobs; ++j) {
+    ModeJob& jb = G.job[j];
+    jb.tile_begin = tot;
+    tot += (int64_t)jb.tiles_i * ceil_div((int64_t)jb.tiles_a * (mode1 ? 1 : jb.nb), sup);
+  }
+  G.total_tiles = tot;
+  G.tiles_per_job = G.njobs > 0 ? tot / G.njobs : 0;
+  for (int j = 0; j < G.njobs; ++j)
+    if (G.job[j].tile_begin != (int64_t)j * G.tiles_per_job) G.tiles_per_job = 0;
+  if (tot == 0) return SETD_OK;
+  double fl = 0.0, by = 0.0;
+  if (prof_on()) job_work(J, 8, 8, 4, fl, by);
+  ProfScope prof(s, mode1 ? kProfMode1LP : kProfModeBLP, fl, by);
+  bool swap = false;
+  for (int j = 0; j < G.njobs; ++j) swap = swap || G.job[j].nterms > 1 || G.job[j].n > kPanelK;
+  const int64_t pxcd = ceil_div(tot, 8);
+  const dim3 grid((unsigned)(pxcd * 8));
+  auto kern = fuse_next ? gemm_i8_kernel<true, false, true>
+             : mode1     ? (swap ? gemm_i8_kernel<true, true, false> : gemm_i8_kernel<true, false, false>)
+                         : (swap ? gemm_i8_kernel<false, true, false> : gemm_i8_kernel<false, false, false>);
+  hipLaunchKernelGGL(kern, grid, dim3(512), 0, s, G, pxcd, sup, fuse_next);
+  SETD_LAUNCHED();
+  return SETD_OK;
+}
+
+}  // namespace
+
+int launch_mode_i8(ModeJobs& J, bool mode1, void* ws, size_t ws_bytes, hipStream_t s, bool presliced, int fuse_next) {
   if (J.njobs == 0) return SETD_OK;
+  if (fuse_next != 0) {
+    bool ok = mode1 && (fuse_next == kGroupCols || fuse_next == 2 * kGroupCols);
+    for (int j = 0; j < J.njobs; ++j)
+      ok = ok && J.job[j].nterms == 1 && J.job[j].n <= kPanelK && J.job[j].nb % fuse_next == 0;
+    if (!ok) {
+      set_error("int8 fused slicing needs mode 1, one term, n <= %d and a next mode of %d or %d", kPanelK, kGroupCols,
+                2 * kGroupCols);
+      return SETD_EINVAL;
+    }
+  }
+  if (presliced) return launch_gemm_i8(J, mode1, s, fuse_next);
   // 1. one digit buffer per distinct input tensor of the launch
   const void* inputs[kMaxJobs * kMaxTerms];
   int ninputs = 0;
@@ -566,41 +774,9 @@ int launch_mode_i8(ModeJobs& J, bool mode1, void* ws, size_t ws_bytes, hipStream
       hipLaunchKernelGGL(slice_i8_kernel<false>, dim3((unsigned)(pxcd * 8)), dim3(256), 0, s, S, pxcd);
     SETD_LAUNCHED();
   }
-  // 3. the digit GEMM: runs of `sup` column groups per workgroup, sized for
-  // about kGemmWgPerCu workgroups per compute unit over the launch
-  ModeJobs G = J;
-  int64_t pairs = 0;
-  for (int j = 0; j < G.njobs; ++j) {
-    ModeJob& jb = G.job[j];
-    jb.tiles_i = (int)ceil_div(jb.n, kPanelRows);
-    jb.tiles_a = (int)ceil_div(mode1 ? jb.nb : jb.na, kGroupCols);
-    pairs += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
-  }
-  const int sup = (int)std::min<int64_t>(kMaxSup, std::max<int64_t>(1, pairs / (kCus * kGemmWgPerCu)));
-  int64_t tot = 0;
-  for (int j = 0; j < G.njobs; ++j) {
-    ModeJob& jb = G.job[j];
-    for (int t = 0; t < jb.nterms; ++t) jb.X[t] = (char*)ws + (size_t)slot_of[j][t] * per;
-    jb.tile_begin = tot;
-    tot += (int64_t)jb.tiles_i * ceil_div((int64_t)jb.tiles_a * (mode1 ? 1 : jb.nb), sup);
-  }
-  G.total_tiles = tot;
-  G.tiles_per_job = G.njobs > 0 ? tot / G.njobs : 0;
-  for (int j = 0; j < G.njobs; ++j)
-    if (G.job[j].tile_begin != (int64_t)j * G.tiles_per_job) G.tiles_per_job = 0;
-  if (tot == 0) return SETD_OK;
-  double fl = 0.0, by = 0.0;
-  if (prof_on()) job_work(J, 8, 8, 4, fl, by);
-  ProfScope prof(s, mode1 ? kProfMode1LP : kProfModeBLP, fl, by);
-  bool swap = false;
-  for (int j = 0; j < G.njobs; ++j) swap = swap || G.job[j].nterms > 1 || G.job[j].n > kPanelK;
-  const int64_t pxcd = ceil_div(tot, 8);
-  const dim3 grid((unsigned)(pxcd * 8));
-  auto kern = mode1 ? (swap ? gemm_i8_kernel<true, true> : gemm_i8_kernel<true, false>)
-                    : (swap ? gemm_i8_kernel<false, true> : gemm_i8_kernel<false, false>);
-  hipLaunchKernelGGL(kern, grid, dim3(512), 0, s, G, pxcd, sup);
-  SETD_LAUNCHED();
-  return SETD_OK;
+  for (int j = 0; j < J.njobs; ++j)
+    for (int t = 0; t < J.job[j].nterms; ++t) J.job[j].X[t] = (char*)ws + (size_t)slot_of[j][t] * per;
+  return launch_gemm_i8(J, mode1, s, fuse_next);
 }
 
 }  // namespace setd

@@ -110,11 +110,13 @@ struct LaunchKind {
   DType out;
   void* i8ws = nullptr;      // digit buffers (SETD_PREC_I8X4)
   size_t i8bytes = 0;
+  bool presliced = false;    // I8X4: the jobs' inputs are digit buffers already
+  int fuse_next = 0;         // I8X4, mode 1: emit the mode-2 digits of this n2
 };
 
 int launch_jobs(ModeJobs& J, const LaunchKind& k, hipStream_t s) {
   if (k.prec == SETD_PREC_F64) return k.mode1 ? launch_mode1_f64(J, s) : launch_modeB_f64(J, s);
-  if (k.prec == SETD_PREC_I8X4) return launch_mode_i8(J, k.mode1, k.i8ws, k.i8bytes, s);
+  if (k.prec == SETD_PREC_I8X4) return launch_mode_i8(J, k.mode1, k.i8ws, k.i8bytes, s, k.presliced, k.fuse_next);
   return k.mode1 ? launch_mode1_lp(J, k.prec, k.out, s) : launch_modeB_lp(J, k.prec, k.out, s);
 }
 
@@ -177,39 +179,61 @@ int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, i
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) N *= dims[mu];
   const DType mid = fp32_storage(prec) ? DType::F32 : DType::F64;
-  const LaunchKind k1{true, prec, mid, i8ws, i8bytes}, kb{false, prec, mid, i8ws, i8bytes},
+  // I8X4 with n1 <= 256 and n2 in {128, 256}: the mode-1 products emit the
+  // mode-2 digits straight into one buffer per chain (the first slots of the
+  // workspace; the slicing passes get the rest), and mode 2 reads them
+  int nchains = 0;
+  for (int o = 0; o < nouts; ++o) nchains += outs[o].nterms;
+  const size_t slot = prec == SETD_PREC_I8X4 ? i8_slot_bytes(d, dims) : 0;
+  const bool fuse = prec == SETD_PREC_I8X4 && d >= 2 && dims[0] <= 256 && (dims[1] == 128 || dims[1] == 256) &&
+                    (size_t)(nchains + 1) * slot <= i8bytes;
+  char* chain_digits = (char*)i8ws;
+  auto chain_slot = [&](int chain) { return (void*)(chain_digits + (size_t)chain * slot); };
+  LaunchKind k1{true, prec, mid, i8ws, i8bytes}, kb{false, prec, mid, i8ws, i8bytes},
       klast{false, prec, DType::F64, i8ws, i8bytes};
+  if (fuse) {
+    k1.i8ws = chain_digits + (size_t)nchains * slot;
+    k1.i8bytes = i8bytes - (size_t)nchains * slot;
+    k1.fuse_next = dims[1];
+  }
   ModeJobs J;
   J.njobs = 0;
-  // mode 1 -> Y1
+  // mode 1 -> Y1 (or the mode-2 digits)
+  int chain = 0;
   for (int o = 0; o < nouts; ++o)
-    for (int t = 0; t < outs[o].nterms; ++t) {
+    for (int t = 0; t < outs[o].nterms; ++t, ++chain) {
       const TuckerTerm& tm = outs[o].term[t];
-      SETD_TRY(push(J, mk_job(tm.X, tm.P[0], 1.0, tm.Y1, nullptr, 1, dims[0], N / dims[0]), k1, s));
+      void* y = fuse ? chain_slot(chain) : tm.Y1;
+      SETD_TRY(push(J, mk_job(tm.X, tm.P[0], 1.0, y, nullptr, 1, dims[0], N / dims[0]), k1, s));
     }
   SETD_TRY(flush(J, k1, s));
   // inner modes, ping-pong Y1 <-> Y2
   int64_t na = dims[0];
   for (int mu = 1; mu < d - 1; ++mu) {
     const int64_t nb = N / (na * dims[mu]);
+    LaunchKind k = kb;
+    k.presliced = fuse && mu == 1;
+    chain = 0;
     for (int o = 0; o < nouts; ++o)
-      for (int t = 0; t < outs[o].nterms; ++t) {
+      for (int t = 0; t < outs[o].nterms; ++t, ++chain) {
         const TuckerTerm& tm = outs[o].term[t];
-        const void* src = (mu % 2 == 1) ? tm.Y1 : tm.Y2;
+        const void* src = k.presliced ? chain_slot(chain) : (mu % 2 == 1) ? tm.Y1 : tm.Y2;
         void* dst = (mu % 2 == 1) ? tm.Y2 : tm.Y1;
-        SETD_TRY(push(J, mk_job(src, tm.P[mu], 1.0, dst, nullptr, na, dims[mu], nb), kb, s));
+        SETD_TRY(push(J, mk_job(src, tm.P[mu], 1.0, dst, nullptr, na, dims[mu], nb), k, s));
       }
-    SETD_TRY(flush(J, kb, s));
+    SETD_TRY(flush(J, k, s));
     na *= dims[mu];
   }
   // last mode: terms summed along the contraction, base added
   const int mu = d - 1;
+  klast.presliced = fuse && mu == 1;
+  chain = 0;
   for (int o = 0; o < nouts; ++o) {
     ModeJob jb{};
     jb.nterms = outs[o].nterms;
-    for (int t = 0; t < outs[o].nterms; ++t) {
+    for (int t = 0; t < outs[o].nterms; ++t, ++chain) {
       const TuckerTerm& tm = outs[o].term[t];
-      jb.X[t] = (mu % 2 == 1) ? tm.Y1 : tm.Y2;
+      jb.X[t] = klast.presliced ? chain_slot(chain) : (mu % 2 == 1) ? tm.Y1 : tm.Y2;
       jb.P[t] = tm.P[mu];
       jb.scale[t] = tm.scale;
     }
@@ -930,11 +954,12 @@ int setd_ctx_create(setd_ctx** out, int d, const int64_t* dims, int ncomp, const
       }
     c->aux = take(1);
   }
-  // int8 digit buffers: one per input of the largest launch (the phi_1 group:
-  // 3 stages x nterms x ncomp)
+  // int8 digit buffers: one per chain of the largest group (the phi_1 group:
+  // 3 stages x nterms x ncomp) for the fused mode-2 digits, as many again
+  // for the inputs of the slicing passes
   if (c->prec == SETD_PREC_I8X4) {
     const size_t slot = i8_slot_bytes(d, c->dims);
-    if ((rc = c->i8_mem.alloc((size_t)3 * c->nterms * ncomp * slot)) != SETD_OK) return fail(rc);
+    if ((rc = c->i8_mem.alloc((size_t)6 * c->nterms * ncomp * slot)) != SETD_OK) return fail(rc);
   }
   if ((rc = build_bank(c, s)) != SETD_OK) return fail(rc);
   *out = c;

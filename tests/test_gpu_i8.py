@@ -177,3 +177,40 @@ def test_i8_trajectory_against_stored_oracle(n):
             en = abs(np.linalg.norm(f) - norms[(name, "l2")]) / norms[(name, "l2")]
             say("  step %d field %s: samples rel_l2 %.3e rel_inf %.3e norm %.3e" % (step, name, e2, ei, en))
             assert e2 < TOL and ei < TOL and en < TOL, (n, step, name, e2, ei, en)
+
+
+@pytest.mark.parametrize("dims", [(100, 256, 7), (64, 128, 5), (256, 256, 3), (37, 256), (130, 128)])
+def test_fused_mode2_digits_i8(dims):
+    """Grids whose second side is 128 or 256, where the mode-1 products emit
+    the digits of the mode-2 operand directly instead of an FP64
+    intermediate: ragged first and third sides, a partial last row panel
+    (rows past n1 must not touch other fibres), and the 2D form in which
+    mode 2 is also the last mode.  Same bar as the unfused split action."""
+    prob = wl.fhn_3d(dims=dims) if len(dims) == 3 else wl.schnakenberg_2d(dims[0], dims[1])
+    A = [[dev(M) for M in Ac] for Ac in prob.A]
+    ctx = setd.Context(prob.dims, A, prob.tau, prec=I8)
+    bank = oracle.etd.PhiBank(prob.A[1], prob.tau)
+    V = wl.random_tensor(prob.dims, 11)
+    Wd = torch().zeros(prob.N, dtype=torch().float64, device="cuda")
+    say("fused i8", dims)
+    ctx.split_phi_apply(1, 2, setd.STAGE_F, dev(V), Wd, scale=1.0, beta=0.0)
+    e = rel_l2(host(Wd, prob.dims), bank.split_apply(2, "f", V))
+    say("  rel_l2 %.3e" % e)
+    assert e < KTOL * 10, (dims, e)
+
+
+def test_fused_mode2_digits_nonfinite_i8():
+    """A NaN in the operand of the fused form: the fibres it reaches get the
+    non-finite exponent and every output they feed is NaN, as in the
+    oracle."""
+    prob = wl.schnakenberg_2d(37, 256)
+    A = [[dev(M) for M in Ac] for Ac in prob.A]
+    ctx = setd.Context(prob.dims, A, prob.tau, prec=I8)
+    bank = oracle.etd.PhiBank(prob.A[0], prob.tau)
+    V = wl.random_tensor(prob.dims, 12)
+    V[5, 77] = np.nan
+    Wd = torch().zeros(prob.N, dtype=torch().float64, device="cuda")
+    ctx.split_phi_apply(0, 1, setd.STAGE_F, dev(V), Wd, scale=1.0, beta=0.0)
+    got = host(Wd, prob.dims)
+    ref = bank.split_apply(1, "f", V)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
