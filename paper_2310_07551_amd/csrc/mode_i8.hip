@@ -303,38 +303,50 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   const int64_t rowbytes = 4 * (int64_t)ldp;
   const int64_t ntot16 = (ntot + 15) & ~(int64_t)15;   // fibres of the digit tiles
 
-  // column of this lane in group q of the run (validity, global fibre index)
-  auto column = [&](int q, int64_t& ca, int64_t& fib) __attribute__((always_inline)) {
-    const int64_t grp = grp0 + q;
-    const int64_t ct = MODE1 ? grp : grp % jb.tiles_a;
-    const int64_t bslab = MODE1 ? 0 : grp / jb.tiles_a;
-    ca = ct * kGroupCols + kWaveCols * wave + l;
-    fib = MODE1 ? ca : ca + na * bslab;
-  };
-  // item -> (group of the run, term, chunk)
-  auto decode = [&](int i, int& q, int& tm, int& ci) __attribute__((always_inline)) {
-    ci = i % nch;
-    tm = (i / nch) % nterms;
-    q = i / (nch * nterms);
-  };
-  // tensor digits of item i, k-step k: this lane's 64 bytes
-  auto bptr = [&](int i, int k64) __attribute__((always_inline)) {
+  // Position of an item in the run: group q (column group ct of slab
+  // bslab), term tm, contraction chunk ci.  Items advance incrementally: a
+  // 64-bit division per item costs more scalar instructions than its k-steps.
+  struct Pos {
     int q, tm, ci;
-    decode(i, q, tm, ci);
+    int64_t ct, bslab;
+  };
+  auto first_pos = [&]() __attribute__((always_inline)) {
+    Pos p{0, 0, 0, MODE1 ? grp0 : grp0 % jb.tiles_a, MODE1 ? 0 : grp0 / jb.tiles_a};
+    return p;
+  };
+  auto advance = [&](Pos p) __attribute__((always_inline)) {
+    if (++p.ci == nch) {
+      p.ci = 0;
+      if (++p.tm == nterms) {
+        p.tm = 0;
+        ++p.q;
+        if (++p.ct == jb.tiles_a && !MODE1) {
+          p.ct = 0;
+          ++p.bslab;
+        }
+      }
+    }
+    return p;
+  };
+  // column of this lane in the item's group (validity, global fibre index)
+  auto column = [&](const Pos& p, int64_t& ca, int64_t& fib) __attribute__((always_inline)) {
+    ca = p.ct * kGroupCols + kWaveCols * wave + l;
+    fib = MODE1 ? ca : ca + na * p.bslab;
+  };
+  // tensor digits of an item, k-step k: this lane's 4 x 16 bytes (1 KB apart)
+  auto bptr = [&](const Pos& p, int k64) __attribute__((always_inline)) {
     int64_t ca, fib;
-    column(q, ca, fib);
-    const uint8_t* D = (const uint8_t*)jb.X[tm];
+    column(p, ca, fib);
+    const uint8_t* D = (const uint8_t*)jb.X[p.tm];
     const int64_t f = ca < nfib ? fib : 0;
-    return D + ((f >> 4) * (ldp / 64) + (ci * kPanelK + k64) / 64) * (int64_t)kTileBytes + 16 * (16 * g + (f & 15));
+    return D + ((f >> 4) * (ldp / 64) + (p.ci * kPanelK + k64) / 64) * (int64_t)kTileBytes + 16 * (16 * g + (f & 15));
   };
   // panel of item i: thread tid holds 16-byte unit `lane` of rows wave + 8 r
   v4i pn[8];
   int pen = 0;
-  auto fetch_panel = [&](int i) __attribute__((always_inline)) {
-    int q, tm, ci;
-    decode(i, q, tm, ci);
-    const uint8_t* P = (const uint8_t*)jb.P[tm];
-    const int kc = ci * kPanelK;
+  auto fetch_panel = [&](const Pos& p) __attribute__((always_inline)) {
+    const uint8_t* P = (const uint8_t*)jb.P[p.tm];
+    const int kc = p.ci * kPanelK;
     const int units = (ldp - kc < kPanelK ? ldp - kc : kPanelK) / 4;
 #pragma unroll
     for (int r = 0; r < 8; ++r)
@@ -347,11 +359,11 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     for (int r = 0; r < 8; ++r) *(v4i*)(panel[buf] + (wave + 8 * r) * kPanelRow + 16 * lane) = pn[r];
     if (tid < kPanelRows) pexp[buf][tid] = pen;
   };
-  auto same_panel = [&](int i, int j) __attribute__((always_inline)) {   // items i and j use one panel (always, without SWAP)
-    return !SWAP || (i % (nch * nterms)) == (j % (nch * nterms));
+  auto same_panel = [&](const Pos& a, const Pos& b) __attribute__((always_inline)) {   // always, without SWAP
+    return !SWAP || (a.tm == b.tm && a.ci == b.ci);
   };
 
-  fetch_panel(0);
+  fetch_panel(first_pos());
   store_panel(0);
   int pb = 0;
   __syncthreads();
@@ -369,19 +381,23 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
 
   // state of the current item
   int i = 0, q = 0, tm = 0, ci = 0, kend = 0, ex = 0;
+  Pos cur = first_pos(), nxt = cur;
   int64_t ca = 0, fib = 0;
   const uint8_t* bcur = nullptr;
   const uint8_t* bnext = nullptr;
   auto begin_item = [&]() __attribute__((always_inline)) {
-    decode(i, q, tm, ci);
-    column(q, ca, fib);
+    q = cur.q;
+    tm = cur.tm;
+    ci = cur.ci;
+    column(cur, ca, fib);
+    nxt = advance(cur);
     const int kc = ci * kPanelK;
     const int kw = ldp - kc < kPanelK ? ldp - kc : kPanelK;
     kend = n - kc < kw ? n - kc : kw;
     // unconditional (clamped) for the same reason as the digit loads below
     ex = ((const int*)((const uint8_t*)jb.X[tm] + ntot16 * rowbytes))[ca < nfib ? fib : 0];
-    bcur = bptr(i, 0);
-    bnext = i + 1 < nitems ? bptr(i + 1, 0) : bcur;   // after the last item: a harmless reload
+    bcur = bptr(cur, 0);
+    bnext = i + 1 < nitems ? bptr(nxt, 0) : bcur;   // after the last item: a harmless reload
   };
   // FUSE (mode 1 only, the next mode's n2 = nnext in {128, 256}): instead of
   // the FP64 product, the digit planes of the next mode's operand.  Column b
@@ -397,9 +413,8 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   auto fused_digits = [&](int q) __attribute__((always_inline)) {
     if constexpr (FUSE) {
       const int g2 = nnext / kGroupCols;
-      const int64_t grp = grp0 + q;
-      const int half = (int)(grp % g2);
-      const int64_t i3 = grp / g2;
+      const int half = g2 == 2 ? (int)(cur.ct & 1) : 0;   // MODE1: the group is ct
+      const int64_t i3 = g2 == 2 ? cur.ct >> 1 : cur.ct;
       double* hb = (double*)panel[1];   // [64 rows][kHbPitch] first-group values
       typedef unsigned short us2 __attribute__((ext_vector_type(2)));
       us2 pk[8];
@@ -511,7 +526,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         } else if (ca < nfib) {
           double* __restrict__ Y = (double*)jb.Y;
           const double* __restrict__ base = (const double*)jb.base;
-          const int64_t slab = MODE1 ? 0 : na * (int64_t)n * ((grp0 + q) / jb.tiles_a);
+          const int64_t slab = MODE1 ? 0 : na * (int64_t)n * cur.bslab;
           auto off = [&](int ii) __attribute__((always_inline)) { return MODE1 ? ii + (int64_t)n * ca : ca + na * (int64_t)ii + slab; };
           if (base) {   // base values in flight eight at a time (rows past n read row n - 1)
 #pragma unroll
@@ -538,9 +553,14 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
               *(d2*)(Y + off(i0) + 2) = d2{out[m][2], out[m][3]};
               continue;
             }
+            if (row0 + kPanelRows <= n) {   // the whole panel is inside: no per-row branches
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (i0 + r < n) Y[off(i0 + r)] = out[m][r];
+              for (int r = 0; r < 4; ++r) Y[off(i0 + r)] = out[m][r];
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (i0 + r < n) Y[off(i0 + r)] = out[m][r];
+            }
           }
         }
 #pragma unroll
@@ -549,9 +569,9 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
           for (int r = 0; r < 4; ++r) out[m][r] = 0.0;
       }
     }
-    if (i + 1 < nitems && !same_panel(i, i + 1)) {
+    if (i + 1 < nitems && !same_panel(cur, nxt)) {
       // every wave is past its reads of panel[pb ^ 1] (an earlier item's)
-      fetch_panel(i + 1);
+      fetch_panel(nxt);
       store_panel(pb ^ 1);
       __syncthreads();
       pb ^= 1;
@@ -609,6 +629,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       }
       end_item();
       if (++i == nitems) break;
+      cur = nxt;
       begin_item();
     }
   };
@@ -633,6 +654,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       if (odd) kstep(k, bA, bB);   // the next item's first digits land in bB
       end_item();
       if (++i == nitems) break;
+      cur = nxt;
       begin_item();
       if (odd) {
 #pragma unroll
@@ -695,7 +717,7 @@ int launch_gemm_i8(const ModeJobs& J, bool mode1, hipStream_t s, int fuse_next) 
     if (G.job[j].tile_begin != (int64_t)j * G.tiles_per_job) G.tiles_per_job = 0;
   if (tot == 0) return SETD_OK;
   double fl = 0.0, by = 0.0;
-  if (prof_on()) job_work(J, 8, 8, 4, fl, by);
+  if (prof_on()) job_work(J, 4, fuse_next ? 4 : 8, 4, fl, by);   // digits in, FP64 (or digits) out
   ProfScope prof(s, mode1 ? kProfMode1LP : kProfModeBLP, fl, by);
   bool swap = false;
   for (int j = 0; j < G.njobs; ++j) swap = swap || G.job[j].nterms > 1 || G.job[j].n > kPanelK;
