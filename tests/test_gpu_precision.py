@@ -152,3 +152,30 @@ def test_tucker_bf16x2_two_term():
     e = rel_err(host(Wd, dims), oracle.tucker(T, Ls))
     say("  bf16x2 tucker rel %.3e" % e)
     assert e < TOL_BF16X2
+
+
+@pytest.mark.parametrize("dims", [(256, 256, 4), (192, 128, 192), (256, 64, 256)])
+def test_f32_panel_kernels_match_register_kernels(dims, monkeypatch):
+    """The FP32 mode-1 LDS-panel kernel (interior products with
+    192 <= n <= 256, n % 64 == 0) issues the same matrix-core products in the
+    same k order as the register-tile kernel and applies the scale the same
+    way, so the two paths agree bit for bit, also when modes >= 2 follow on
+    the register kernels; 4 x 2 tiles force the register path.  Both within
+    1e-5 of the oracle."""
+    T = wl.random_tensor(dims, 21)
+    Ls = [wl.random_matrix(n, 30 + k, scale=1.0 / np.sqrt(n)) for k, n in enumerate(dims)]
+    W0 = wl.random_tensor(dims, 22)
+
+    def run():
+        Wd = dev(W0)
+        setd.tucker_apply(dev(T), Wd, dims, [dev(L) for L in Ls], alpha=0.5, beta=1.0, prec=setd.PREC_F32)
+        return host(Wd, dims)
+
+    say("f32 panel vs register", dims)
+    panel = run()
+    monkeypatch.setenv("SETD_TILE_F32_MODE1", "4x2")
+    monkeypatch.setenv("SETD_TILE_F32_MODEB", "4x2")
+    reg = run()
+    assert np.array_equal(panel, reg)
+    ref = 0.5 * oracle.tucker(T, Ls)
+    assert rel_err(panel - W0, ref) < TOL
