@@ -258,7 +258,8 @@ __global__ void __launch_bounds__(64, 2) modeB_f32c_kernel(const ModeJobs J, int
     const float* __restrict__ xb = (const float*)jb.X[term] + slab + arow + na * g;
     const float* __restrict__ pbp = (const float*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
     const float sc = (float)jb.scale[term];
-    constexpr int KB = 4;   // k-steps per chunk
+    // k-steps per register block: 2 (at 3D FHN 256^3 97.4 TFLOP/s against 95.3 for 4 and 96.5 for 8)
+    constexpr int KB = 2;
     auto mmablk = [&](float (*xr)[TM], float (*pr)[TN]) {
 #pragma unroll
       for (int k = 0; k < KB; ++k)
@@ -451,6 +452,8 @@ __global__ void __launch_bounds__(512, 1) mode1_lds32_kernel(const ModeJobs J, i
 
 // ---------------------------------------------------------------------------
 // MODE as for the modes >= 2 kernel (2: n % 32 == 0, nb % (16 TN) == 0).
+// One wave per SIMD: bounding these kernels to two (128 registers) made them
+// spill and run at a fifth of the speed (3D FHN 256^3: 26 against 115 steps/s).
 template <int NP, int TM, int TN, int MODE, typename TOut>
 __global__ void __launch_bounds__(64) mode1_bf16_kernel(const ModeJobs J, int64_t per_xcd) {
   constexpr bool VEC = MODE >= 1;
