@@ -80,9 +80,10 @@ struct TuckerOut {
 // exceed kMaxJobs).  dims has d >= 2 entries.  With a reduced-precision
 // `prec`, term inputs and Y1/Y2 are FP32 and the outputs FP64.
 // SETD_PREC_I8X4 needs digit buffers of i8_slot_bytes each (i8ws): one per
-// distinct input of a launch, and for the fused mode-1 -> mode-2 form (n2 in
-// {128, 256}) one per chain (term of an output) besides; without room for
-// both the chain runs unfused.
+// distinct input of a launch, and for the fused forms one (mode 1 -> mode 2,
+// n2 in {128, 256}) or two (d = 3 in the order 3, 1, 2 with n1 and n2 in
+// {128, 256}) per chain (term of an output) besides; without room for them
+// a group runs the less fused form.
 int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s,
                      void* i8ws = nullptr, size_t i8bytes = 0);
 // Bytes of one int8 digit buffer for any mode of the grid.

@@ -399,11 +399,15 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     bcur = bptr(cur, 0);
     bnext = i + 1 < nitems ? bptr(nxt, 0) : bcur;   // after the last item: a harmless reload
   };
-  // FUSE (mode 1 only, the next mode's n2 = nnext in {128, 256}): instead of
-  // the FP64 product, the digit planes of the next mode's operand.  Column b
-  // of this product is (i2, i3) = (b % n2, b / n2), so the nnext / 128
+  // FUSE (one term, n <= 256; the next mode's size nnext in {128, 256}):
+  // instead of the FP64 product, the digit planes of the operand of the next
+  // mode, the one whose index runs fastest along this product's columns.
+  // Mode 1: column b is (i2, i3) = (b % n2, b / n2), so the nnext / 128
   // consecutive groups of a run that share i3 hold, for each of the 64 rows
-  // i1, the whole mode-2 fibre c2 = i1 + n i3.  The first group's values wait
+  // i1, the whole mode-2 fibre i1 + n1 i3.  Modes >= 2 (the next mode is 1):
+  // column a is (i1, a / n1), and the groups sharing a / n1 hold, for each
+  // row i and slab b, the whole mode-1 fibre a / n1 + (na / n1)(i + n b).
+  // The first group's values wait
   // in LDS (the second panel buffer, unused without SWAP); at the last group
   // the fibre exponents (the maximum over both groups of the frexp exponent
   // of every value, reduced across lanes as packed 16-bit fields: zero -> 0,
@@ -413,8 +417,12 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   auto fused_digits = [&](int q) __attribute__((always_inline)) {
     if constexpr (FUSE) {
       const int g2 = nnext / kGroupCols;
-      const int half = g2 == 2 ? (int)(cur.ct & 1) : 0;   // MODE1: the group is ct
-      const int64_t i3 = g2 == 2 ? cur.ct >> 1 : cur.ct;
+      const int half = g2 == 2 ? (int)(cur.ct & 1) : 0;   // which group of the fibre set
+      const int64_t set = g2 == 2 ? cur.ct >> 1 : cur.ct;   // MODE1: i3; modes >= 2: a / n1
+      // the next mode's fibre through row R of this product
+      auto fibre = [&](int R) __attribute__((always_inline)) {
+        return MODE1 ? row0 + R + (int64_t)n * set : set + (na / nnext) * (row0 + R + (int64_t)n * cur.bslab);
+      };
       double* hb = (double*)panel[1];   // [64 rows][kHbPitch] first-group values
       typedef unsigned short us2 __attribute__((ext_vector_type(2)));
       us2 pk[8];
@@ -450,7 +458,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         return;
       }
       __syncthreads();
-      const int64_t ntot2 = (int64_t)n * (nb / nnext);   // fibres of the next mode
+      const int64_t ntot2 = (int64_t)n * (MODE1 ? nb : na * nb) / nnext;   // fibres of the next mode
       const int ldp2 = nnext, nks2 = nnext / 64;
       uint8_t* __restrict__ Dn = (uint8_t*)jb.Y;
       if (tid < kPanelRows) {
@@ -460,8 +468,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         const int E = bmax == 0 ? 0 : (bmax == 0xFFFF ? kBadExp : bmax - 2048);
         erow[tid] = E;
         if (row0 + tid < n) {
-          const int64_t c2 = row0 + tid + (int64_t)n * i3;
-          ((int*)(Dn + ((ntot2 + 15) & ~(int64_t)15) * 4 * (int64_t)ldp2))[c2] = E;
+          ((int*)(Dn + ((ntot2 + 15) & ~(int64_t)15) * 4 * (int64_t)ldp2))[fibre(tid)] = E;
         }
       }
       __syncthreads();
@@ -487,7 +494,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
             const uint32_t y = __builtin_amdgcn_perm(w3, w2, sel);   // of values 2, 3
             const uint32_t d = __builtin_amdgcn_perm(y, x, 0x05040100u);
             if (row0 + R < n) {
-              const int64_t c2 = row0 + R + (int64_t)n * i3;
+              const int64_t c2 = fibre(R);
               const int i2 = kGroupCols * h + kWaveCols * wave + l;
               uint8_t* dst = Dn + ((c2 >> 4) * nks2 + (i2 >> 6)) * (int64_t)kTileBytes + kPlaneBytes * t4 +
                              16 * (16 * ((i2 >> 4) & 3) + (c2 & 15)) + 4 * (l >> 2);
@@ -723,7 +730,7 @@ int launch_gemm_i8(const ModeJobs& J, bool mode1, hipStream_t s, int fuse_next) 
   for (int j = 0; j < G.njobs; ++j) swap = swap || G.job[j].nterms > 1 || G.job[j].n > kPanelK;
   const int64_t pxcd = ceil_div(tot, 8);
   const dim3 grid((unsigned)(pxcd * 8));
-  auto kern = fuse_next ? gemm_i8_kernel<true, false, true>
+  auto kern = fuse_next ? (mode1 ? gemm_i8_kernel<true, false, true> : gemm_i8_kernel<false, false, true>)
              : mode1     ? (swap ? gemm_i8_kernel<true, true, false> : gemm_i8_kernel<true, false, false>)
                          : (swap ? gemm_i8_kernel<false, true, false> : gemm_i8_kernel<false, false, false>);
   hipLaunchKernelGGL(kern, grid, dim3(512), 0, s, G, pxcd, sup, fuse_next);
@@ -736,12 +743,13 @@ int launch_gemm_i8(const ModeJobs& J, bool mode1, hipStream_t s, int fuse_next) 
 int launch_mode_i8(ModeJobs& J, bool mode1, void* ws, size_t ws_bytes, hipStream_t s, bool presliced, int fuse_next) {
   if (J.njobs == 0) return SETD_OK;
   if (fuse_next != 0) {
-    bool ok = mode1 && (fuse_next == kGroupCols || fuse_next == 2 * kGroupCols);
+    bool ok = fuse_next == kGroupCols || fuse_next == 2 * kGroupCols;
     for (int j = 0; j < J.njobs; ++j)
-      ok = ok && J.job[j].nterms == 1 && J.job[j].n <= kPanelK && J.job[j].nb % fuse_next == 0;
+      ok = ok && J.job[j].nterms == 1 && J.job[j].n <= kPanelK &&
+           (mode1 ? J.job[j].nb % fuse_next == 0 : J.job[j].na % fuse_next == 0);
     if (!ok) {
-      set_error("int8 fused slicing needs mode 1, one term, n <= %d and a next mode of %d or %d", kPanelK, kGroupCols,
-                2 * kGroupCols);
+      set_error("int8 fused slicing needs one term, n <= %d, a next mode of %d or %d dividing the columns", kPanelK,
+                kGroupCols, 2 * kGroupCols);
       return SETD_EINVAL;
     }
   }

@@ -179,12 +179,63 @@ int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, i
   int64_t N = 1;
   for (int mu = 0; mu < d; ++mu) N *= dims[mu];
   const DType mid = fp32_storage(prec) ? DType::F32 : DType::F64;
-  // I8X4 with n1 <= 256 and n2 in {128, 256}: the mode-1 products emit the
-  // mode-2 digits straight into one buffer per chain (the first slots of the
-  // workspace; the slicing passes get the rest), and mode 2 reads them
   int nchains = 0;
   for (int o = 0; o < nouts; ++o) nchains += outs[o].nterms;
   const size_t slot = prec == SETD_PREC_I8X4 ? i8_slot_bytes(d, dims) : 0;
+  auto fusable = [](int m) { return m == 128 || m == 256; };
+  // I8X4, d = 3, n1 and n2 in {128, 256}, n3 <= 256: the products run in the
+  // order 3, 1, 2 (the modes commute), so that both intermediates are emitted
+  // as digits by the product before them: mode 3 writes the mode-1 digits
+  // (slot A of the chain), mode 1 the mode-2 digits (slot B), and only the
+  // inputs are sliced (into the slots after them)
+  if (prec == SETD_PREC_I8X4 && d == 3 && fusable(dims[0]) && fusable(dims[1]) && dims[2] <= 256 &&
+      (size_t)(2 * nchains + 1) * slot <= i8bytes) {
+    char* base_ws = (char*)i8ws;
+    auto slotA = [&](int c) { return (void*)(base_ws + (size_t)c * slot); };
+    auto slotB = [&](int c) { return (void*)(base_ws + (size_t)(nchains + c) * slot); };
+    LaunchKind k3{false, prec, DType::F64, base_ws + (size_t)2 * nchains * slot, i8bytes - (size_t)2 * nchains * slot};
+    k3.fuse_next = dims[0];
+    LaunchKind k1{true, prec, DType::F64, i8ws, i8bytes};
+    k1.presliced = true;
+    k1.fuse_next = dims[1];
+    LaunchKind k2{false, prec, DType::F64, i8ws, i8bytes};
+    k2.presliced = true;
+    ModeJobs J;
+    J.njobs = 0;
+    int c = 0;
+    for (int o = 0; o < nouts; ++o)
+      for (int t = 0; t < outs[o].nterms; ++t, ++c)
+        SETD_TRY(push(J, mk_job(outs[o].term[t].X, outs[o].term[t].P[2], 1.0, slotA(c), nullptr,
+                                (int64_t)dims[0] * dims[1], dims[2], 1), k3, s));
+    SETD_TRY(flush(J, k3, s));
+    c = 0;
+    for (int o = 0; o < nouts; ++o)
+      for (int t = 0; t < outs[o].nterms; ++t, ++c)
+        SETD_TRY(push(J, mk_job(slotA(c), outs[o].term[t].P[0], 1.0, slotB(c), nullptr, 1, dims[0],
+                                (int64_t)dims[1] * dims[2]), k1, s));
+    SETD_TRY(flush(J, k1, s));
+    c = 0;
+    for (int o = 0; o < nouts; ++o) {
+      ModeJob jb{};
+      jb.nterms = outs[o].nterms;
+      for (int t = 0; t < outs[o].nterms; ++t, ++c) {
+        jb.X[t] = slotB(c);
+        jb.P[t] = outs[o].term[t].P[1];
+        jb.scale[t] = outs[o].term[t].scale;
+      }
+      jb.Y = outs[o].Y;
+      jb.base = outs[o].base;
+      jb.na = dims[0];
+      jb.nb = dims[2];
+      jb.n = dims[1];
+      jb.ldp = packed_ld(dims[1]);
+      SETD_TRY(push(J, jb, k2, s));
+    }
+    return flush(J, k2, s);
+  }
+  // I8X4 with n1 <= 256 and n2 in {128, 256}: the mode-1 products emit the
+  // mode-2 digits straight into one buffer per chain (the first slots of the
+  // workspace; the slicing passes get the rest), and mode 2 reads them
   const bool fuse = prec == SETD_PREC_I8X4 && d >= 2 && dims[0] <= 256 && (dims[1] == 128 || dims[1] == 256) &&
                     (size_t)(nchains + 1) * slot <= i8bytes;
   char* chain_digits = (char*)i8ws;
@@ -954,12 +1005,12 @@ int setd_ctx_create(setd_ctx** out, int d, const int64_t* dims, int ncomp, const
       }
     c->aux = take(1);
   }
-  // int8 digit buffers: one per chain of the largest group (the phi_1 group:
-  // 3 stages x nterms x ncomp) for the fused mode-2 digits, as many again
-  // for the inputs of the slicing passes
+  // int8 digit buffers: two per chain of the largest group (the phi_1 group:
+  // 3 stages x nterms x ncomp) for the fused intermediates' digits, and
+  // ncomp + 1 for the inputs of the slicing passes
   if (c->prec == SETD_PREC_I8X4) {
     const size_t slot = i8_slot_bytes(d, c->dims);
-    if ((rc = c->i8_mem.alloc((size_t)6 * c->nterms * ncomp * slot)) != SETD_OK) return fail(rc);
+    if ((rc = c->i8_mem.alloc((size_t)(6 * c->nterms * ncomp + ncomp + 1) * slot)) != SETD_OK) return fail(rc);
   }
   if ((rc = build_bank(c, s)) != SETD_OK) return fail(rc);
   *out = c;

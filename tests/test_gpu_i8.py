@@ -179,13 +179,17 @@ def test_i8_trajectory_against_stored_oracle(n):
             assert e2 < TOL and ei < TOL and en < TOL, (n, step, name, e2, ei, en)
 
 
-@pytest.mark.parametrize("dims", [(100, 256, 7), (64, 128, 5), (256, 256, 3), (37, 256), (130, 128)])
+@pytest.mark.parametrize("dims", [(100, 256, 7), (64, 128, 5), (256, 256, 3), (37, 256), (130, 128),
+                                  (128, 256, 20), (256, 128, 7), (128, 128, 100)])
 def test_fused_mode2_digits_i8(dims):
     """Grids whose second side is 128 or 256, where the mode-1 products emit
     the digits of the mode-2 operand directly instead of an FP64
     intermediate: ragged first and third sides, a partial last row panel
     (rows past n1 must not touch other fibres), and the 2D form in which
-    mode 2 is also the last mode.  Same bar as the unfused split action."""
+    mode 2 is also the last mode.  With n1 in {128, 256} too (3D) the
+    products run in the order 3, 1, 2 and mode 3 emits the mode-1 digits as
+    well (ragged and short third sides, both orders of 128 and 256).  Same
+    bar as the unfused split action."""
     prob = wl.fhn_3d(dims=dims) if len(dims) == 3 else wl.schnakenberg_2d(dims[0], dims[1])
     A = [[dev(M) for M in Ac] for Ac in prob.A]
     ctx = setd.Context(prob.dims, A, prob.tau, prec=I8)
@@ -214,3 +218,17 @@ def test_fused_mode2_digits_nonfinite_i8():
     got = host(Wd, prob.dims)
     ref = bank.split_apply(1, "f", V)
     assert np.array_equal(np.isnan(got), np.isnan(ref))
+
+
+def test_fused_order_312_nonfinite_i8():
+    """A NaN in the operand of the 3, 1, 2 form: every output it reaches
+    through the three products is NaN, the others finite, as in the oracle."""
+    prob = wl.fhn_3d(dims=(128, 128, 9))
+    A = [[dev(M) for M in Ac] for Ac in prob.A]
+    ctx = setd.Context(prob.dims, A, prob.tau, prec=I8)
+    bank = oracle.etd.PhiBank(prob.A[0], prob.tau)
+    V = wl.random_tensor(prob.dims, 13)
+    V[3, 4, 5] = np.nan
+    Wd = torch().zeros(prob.N, dtype=torch().float64, device="cuda")
+    ctx.split_phi_apply(0, 1, setd.STAGE_F, dev(V), Wd, scale=1.0, beta=0.0)
+    assert np.array_equal(np.isnan(host(Wd, prob.dims)), np.isnan(bank.split_apply(1, "f", V)))
