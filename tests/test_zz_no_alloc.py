@@ -29,21 +29,22 @@ def _both(dims, prec, alpha, beta, seed):
     return host(Wa, dims), host(Wb, dims), alpha * oracle.tucker(T, Ls) + beta * W0
 
 
-@pytest.mark.parametrize("prec", [setd.PREC_F64, setd.PREC_F32, setd.PREC_BF16X3])
+@pytest.mark.parametrize("prec", [setd.PREC_F64, setd.PREC_F32, setd.PREC_BF16X3, setd.PREC_I8X4])
 def test_noalloc_matches_allocating_entry_point(prec):
     for dims, alpha, beta, seed in (((64, 96, 80), 1.0, 0.0, 10), ((20, 30, 17), 0.7, 0.5, 20)):
         say("noalloc", prec, dims, alpha, beta)
         ref_lib, got, ref_oracle = _both(dims, prec, alpha, beta, seed)
         assert np.array_equal(got, ref_lib), (prec, dims, np.max(np.abs(got - ref_lib)))
-        tol = 1e-13 if prec == setd.PREC_F64 else 1e-5
+        tol = {setd.PREC_F64: 1e-13, setd.PREC_I8X4: 1e-7}.get(prec, 1e-5)
         assert rel_err(got, ref_oracle) < tol, (prec, dims, rel_err(got, ref_oracle))
 
 
 def test_noalloc_largest_fp64_workload_tensor():
     """128^3 (the 3D FitzHugh-Nagumo grid of the 100-step workload) fits the
-    scratch array in FP64 and in the bf16 split form."""
+    scratch array in FP64, in the bf16 split form and in the int8 slicing
+    form (its digit buffer included)."""
     dims = (128, 128, 128)
-    for prec in (setd.PREC_F64, setd.PREC_BF16X3):
+    for prec in (setd.PREC_F64, setd.PREC_BF16X3, setd.PREC_I8X4):
         assert setd.tucker_workspace_bytes(dims, prec) <= _lib.NOALLOC_SCRATCH_BYTES
         T = random_tensor(dims, 3)
         Ls = [random_matrix(128, 40 + k, scale=0.1) for k in range(3)]
