@@ -302,6 +302,8 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, l = lane & 15;
   const int64_t rowbytes = 4 * (int64_t)ldp;
   const int64_t ntot16 = (ntot + 15) & ~(int64_t)15;   // fibres of the digit tiles
+  // FUSE, modes >= 2: next-mode fibres per row of this product (one division per workgroup)
+  const int64_t fstride = FUSE && !MODE1 ? na / nnext : 0;
 
   // Position of an item in the run: group q (column group ct of slab
   // bslab), term tm, contraction chunk ci.  Items advance incrementally: a
@@ -421,7 +423,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       const int64_t set = g2 == 2 ? cur.ct >> 1 : cur.ct;   // MODE1: i3; modes >= 2: a / n1
       // the next mode's fibre through row R of this product
       auto fibre = [&](int R) __attribute__((always_inline)) {
-        return MODE1 ? row0 + R + (int64_t)n * set : set + (na / nnext) * (row0 + R + (int64_t)n * cur.bslab);
+        return MODE1 ? row0 + R + (int64_t)n * set : set + fstride * (row0 + R + (int64_t)n * cur.bslab);
       };
       double* hb = (double*)panel[1];   // [64 rows][kHbPitch] first-group values
       typedef unsigned short us2 __attribute__((ext_vector_type(2)));
@@ -458,7 +460,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         return;
       }
       __syncthreads();
-      const int64_t ntot2 = (int64_t)n * (MODE1 ? nb : na * nb) / nnext;   // fibres of the next mode
+      const int64_t ntot2 = MODE1 ? n * (nb / nnext) : fstride * n * nb;   // fibres of the next mode
       const int ldp2 = nnext, nks2 = nnext / 64;
       uint8_t* __restrict__ Dn = (uint8_t*)jb.Y;
       if (tid < kPanelRows) {
