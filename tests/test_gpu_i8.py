@@ -180,7 +180,7 @@ def test_i8_trajectory_against_stored_oracle(n):
 
 
 @pytest.mark.parametrize("dims", [(100, 256, 7), (64, 128, 5), (256, 256, 3), (37, 256), (130, 128),
-                                  (128, 256, 20), (256, 128, 7), (128, 128, 100)])
+                                  (128, 256, 20), (256, 128, 7), (128, 128, 100), (128, 128, 300)])
 def test_fused_mode2_digits_i8(dims):
     """Grids whose second side is 128 or 256, where the mode-1 products emit
     the digits of the mode-2 operand directly instead of an FP64
@@ -188,7 +188,8 @@ def test_fused_mode2_digits_i8(dims):
     (rows past n1 must not touch other fibres), and the 2D form in which
     mode 2 is also the last mode.  With n1 in {128, 256} too (3D) the
     products run in the order 3, 1, 2 and mode 3 emits the mode-1 digits as
-    well (ragged and short third sides, both orders of 128 and 256).  Same
+    well (ragged and short third sides, both orders of 128 and 256); a third
+    side above 256 keeps the order 1, 2, 3 with a chunked last mode.  Same
     bar as the unfused split action."""
     prob = wl.fhn_3d(dims=dims) if len(dims) == 3 else wl.schnakenberg_2d(dims[0], dims[1])
     A = [[dev(M) for M in Ac] for Ac in prob.A]
