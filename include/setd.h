@@ -58,13 +58,15 @@ extern "C" {
 #define SETD_PREC_BF16X2  3    /* two-term split x = h + l; h*h, h*l, l*h (three
                                   products): faster, about 16 significant bits */
 #define SETD_PREC_I8X4    4    /* error-free int8 slicing (Ozaki scheme): every
-                                  phi row and tensor fibre as 30-bit integers
-                                  relative to its largest entry, four int8
-                                  digits each; the ten digit products of order
-                                  >= 3 summed exactly in int32 on the int8
-                                  matrix cores, combined in FP64 (about 2^-29
-                                  of |x|max |p|max per product term); FP64
-                                  inputs, intermediates and outputs          */
+                                  phi row and tensor fibre rounded to a 30-bit
+                                  integer relative to its largest entry, four
+                                  int8 digits each; the thirteen digit products
+                                  of order >= 2 summed exactly in int32 on the
+                                  int8 matrix cores, combined in FP64 (about
+                                  2^-29 of |x|max |p|max per product term);
+                                  FP64 inputs, outputs and sums; intermediates
+                                  kept as digits where the next product can
+                                  take them so                               */
 
 /* ---- reaction terms g (eq. twocompdisc: two components u, v) ---- */
 #define SETD_G_NONE         0  /* g = 0; nparams = 0                            */

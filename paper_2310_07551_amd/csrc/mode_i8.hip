@@ -9,14 +9,15 @@
 // with four signed 8-bit digits t_k (t3 in [-64, 64],
 // the others in [-128, 127]).  A product of two entries is then
 //     2^(Ex + Ep - 60) sum_{a, b} t^x_a t^p_b 2^(8 (a + b)),
-// and the pairs with a + b >= 2 (thirteen of the sixteen; the other three
-// weigh at most 2^-44 of |x|max |p|max) are summed over the whole contraction
-// on the int8 matrix cores in int32, one accumulator per order a + b, with no
-// rounding at all (|sum| <= 4 n 2^14 < 2^31 for n <= 4096).  The five
-// accumulators of an output are combined in FP64 and scaled by
-// 2^(Ex + Ep - 12).  The error is the rounding of each operand to 30 bits of
-// its vector's largest entry: at most 2^-30 of |x|max |p|max per product
-// term (unbiased), whatever the cancellation in the sum.
+// and the pairs with a + b >= 2 (thirteen of the sixteen) are summed over
+// the whole contraction on the int8 matrix cores in int32, one accumulator
+// per order a + b, with no rounding at all (|sum| <= 4 n 2^14 < 2^31 for
+// n <= 4096).  The five accumulators of an output are combined in FP64 and
+// scaled by 2^(Ex + Ep - 12).  Per product term the error is the rounding of
+// each operand to 30 bits of its vector's largest entry (2^(E - 31) <= 2^-30
+// of the vector's largest magnitude, unbiased) plus the three dropped pairs,
+// 2^(Ex + Ep - 60) (2^14 + 2 2^22) <= 2^-36 |x|max |p|max: about 2^-29 of
+// |x|max |p|max in all, whatever the cancellation in the sum.
 // This is what the reduced-precision forms of FP32 matrix-core arithmetic
 // cannot give on the 3D FitzHugh-Nagumo workload, whose F = K u + g is about
 // 1e5 times the step's result: their FP32 partial sums round at the scale of
@@ -24,16 +25,18 @@
 //
 // Two kernels.  The slicing kernel reads an FP64 tensor operand once and
 // writes, for every fibre along the contracted mode, its exponent and its
-// four digit planes (4 bytes per entry, zero beyond n) in the order the
-// matrix cores read them; it is bound by HBM and does all the splitting work.
-// The digit GEMM then multiplies the phi digits (sliced once when the matrix
-// is packed) with those planes: a workgroup of 8 waves (two per SIMD) keeps a
-// 64-row panel of the matrix digits in LDS and each wave computes a 64-row x
-// 16-column output tile from it, reading its columns' digits straight from
-// memory (64 contiguous bytes per lane and k-step, the next step's in flight
-// during the current one's products).  Its main loop is loads and MFMAs only;
-// the FP64 combination runs once per output.  Inputs, intermediates and
-// outputs stay FP64.
+// four digit planes (4 bytes per entry, zero beyond n), tiled in the order the
+// matrix cores read them; it is bound by HBM.  The digit GEMM multiplies the
+// phi digits (sliced once when the matrix is packed) with those planes: a
+// workgroup of 8 waves (two per SIMD) keeps a 64-row panel of the matrix
+// digits in LDS, each wave computes 64-row x 16-column output tiles from it,
+// and the workgroup walks a run of column groups as one pipeline with the
+// tensor digits of later k-steps in flight.  The FP64 combination runs once
+// per output.  Where a workgroup's run holds whole fibres of the next mode's
+// operand (mode 1 -> 2 for n2 in {128, 256}; mode 3 -> 1 for n1 in
+// {128, 256}, the 3D Tucker then taken in the order 3, 1, 2), the GEMM emits
+// that operand's digit planes instead of its FP64 product, so only the inputs
+// of a Tucker are sliced.  Inputs, the FP64 combination and outputs are FP64.
 //
 // Lane layout (probed on gfx950): lane (g, l) supplies row l of A and column
 // l of B at 16 k-slots (g, j); both operands use k = 16 g + j of the current

@@ -84,7 +84,8 @@ def test_i8_wide_dynamic_range_and_cancellation():
     setd.tucker_apply(dev(T), Wd, (n, 64), [dev(L), None], prec=I8)
     got = host(Wd, (n, 64))
     ref = L @ T
-    # per term: operand truncations 2 x 2^-29 and the dropped digit pairs 12 x 2^-30 of |x|max |p|max
+    # per term: two operand roundings of 2^-30 and the three dropped digit pairs (2^-36) of
+    # |x|max |p|max, about 2^-29; the bound leaves a factor 8
     bound = n * 2.0 ** -26 * np.abs(L).max(axis=1)[:, None] * np.abs(T).max(axis=0)[None, :]
     assert np.all(np.abs(got - ref) <= bound)
 
