@@ -283,9 +283,9 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
 template <bool MODE1, bool SWAP, bool FUSE>
 __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64_t per_xcd, int sup, int nnext) {
   __shared__ __attribute__((aligned(16))) uint8_t panel[2][kPanelRows * kPanelRow];
-  __shared__ int pexp[2][kPanelRows];
+  __shared__ __attribute__((aligned(16))) int pexp[2][kPanelRows];
   __shared__ int emax[FUSE ? 2 : 1][kGemmWaves][kPanelRows];   // FUSE: biased exponent maxima per half, wave, row
-  __shared__ int erow[kPanelRows];
+  __shared__ __attribute__((aligned(16))) int erow[kPanelRows];
   const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;   // uniform over the block
   const ModeJob& jb = J.job[find_job(J, t)];
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   // non-finite -> the largest) are formed and every value is cut into its
   // digits exactly as the slicing kernel would, a quad of lanes trading bytes
   // so that each lane stores one 4-byte run of one plane.
-  auto fused_digits = [&](int q) __attribute__((always_inline)) {
+  auto fused_digits = [&]() __attribute__((always_inline)) {
     if constexpr (FUSE) {
       const int g2 = nnext / kGroupCols;
       const int half = g2 == 2 ? (int)(cur.ct & 1) : 0;   // which group of the fibre set
@@ -430,7 +430,11 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       };
       double* hb = (double*)panel[1];   // [64 rows][kHbPitch] first-group values
       typedef unsigned short us2 __attribute__((ext_vector_type(2)));
-      us2 pk[8];
+      union U2 {
+        us2 v;
+        int i;
+      };
+      U2 pk[8];   // biased exponents of this lane's 16 values, two to a word
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -439,22 +443,27 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
           int e = 0;
           (void)frexp(v, &e);
           const unsigned short be = v == 0.0 ? 0 : (isfinite(v) ? (unsigned short)(e + 2048) : (unsigned short)0xFFFF);
-          pk[2 * m + (r >> 1)][r & 1] = be;
+          pk[2 * m + (r >> 1)].v[r & 1] = be;
         }
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1)
+      // maximum over the 16 lanes of a row block: swaps within quads, then
+      // the half-row and row mirrors (DPP, no LDS traffic)
+      auto lane_max = [&](auto ctrl) __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          union { us2 v; int i; } a, b;
-          a.v = pk[k];
-          b.i = __shfl_xor(a.i, o, 64);
-          pk[k] = __builtin_elementwise_max(a.v, b.v);
+          U2 o;
+          o.i = __builtin_amdgcn_mov_dpp(pk[k].i, decltype(ctrl)::value, 0xF, 0xF, false);
+          pk[k].v = __builtin_elementwise_max(pk[k].v, o.v);
         }
+      };
+      lane_max(std::integral_constant<int, 0xB1>{});    // quad_perm [1, 0, 3, 2]
+      lane_max(std::integral_constant<int, 0x4E>{});    // quad_perm [2, 3, 0, 1]
+      lane_max(std::integral_constant<int, 0x141>{});   // row_half_mirror
+      lane_max(std::integral_constant<int, 0x140>{});   // row_mirror
       if (l == 0)
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) emax[half][wave][16 * m + 4 * g + r] = pk[2 * m + (r >> 1)][r & 1];
+          for (int r = 0; r < 4; ++r) emax[half][wave][16 * m + 4 * g + r] = pk[2 * m + (r >> 1)].v[r & 1];
       if (half != g2 - 1) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -477,54 +486,101 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         }
       }
       __syncthreads();
-      const int t4 = l & 3;   // this lane's plane after the exchange
-      const uint32_t sel = (uint32_t)t4 | ((uint32_t)(4 + t4) << 8) | 0x0C0C0000u;
+      v4i Ev[4];   // exponents of this lane's rows 16 m + 4 g + r
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h >= g2) break;
-        const bool regs = h == g2 - 1;
+      for (int m = 0; m < 4; ++m) Ev[m] = *(const v4i*)&erow[16 * m + 4 * g];
+      // A quad of lanes holds 4 consecutive values of a row; after a 4 x 4
+      // byte transpose in two pair swaps, lane t4 holds their digit plane t4.
+      const int t4 = l & 3;
+      const uint32_t selA = t4 < 2 ? 0x05040100u : 0x03020706u;    // keep 2 own bytes, take 2 of lane ^ 2
+      const uint32_t selB = (t4 & 1) ? 0x03070105u : 0x06020400u;  // interleave with lane ^ 1
+      // Destination of value (R, i2): tile (c2 / 16) nks2 + i2 / 64, plane t4,
+      // lane slot 16 ((i2 / 16) % 4) + c2 % 16, byte 4 (l / 4); with
+      // i2 = 128 h + 16 wave + l the column part is the same for every row.
+      const uint32_t loff = (uint32_t)((wave >> 2) * kTileBytes + kPlaneBytes * t4 + 256 * (wave & 3) + 4 * (l >> 2));
+      // Row part ((c2 / 16) nks2) kTileBytes + 16 (c2 % 16) = ubase + sm m + sr r + lrow
+      // when the rows come in whole blocks of 16 (n % 16 == 0) whose fibres are
+      // evenly spaced (a multiple of 16 apart for modes >= 2, consecutive from a
+      // multiple of 16 for mode 1).
+      const int64_t tstride = (int64_t)nks2 * kTileBytes;
+      int64_t ubase = 0, sm = 0, sr = 0;
+      uint32_t lrow = 0;
+      bool fast;
+      if constexpr (MODE1) {
+        fast = n % 16 == 0;
+        ubase = ((row0 + (int64_t)n * set) >> 4) * tstride;
+        sm = tstride;
+        sr = 16;
+        lrow = 64 * g;
+      } else {
+        const int64_t fs = fstride >> 4;
+        sr = fs * tstride;
+        fast = n % 16 == 0 && fstride % 16 == 0 && 12 * sr < ((int64_t)1 << 31);
+        ubase = ((set >> 4) + fs * (row0 + (int64_t)n * cur.bslab)) * tstride + 16 * (set & 15);
+        sm = 16 * sr;
+        lrow = (uint32_t)(4 * g * sr);
+      }
+      auto emit = [&](auto from_hb, auto fastc, int h) __attribute__((always_inline)) {
+        constexpr bool kFast = decltype(fastc)::value;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m) {
+          if (kFast && row0 + 16 * m >= n) break;   // whole row blocks
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int R = 16 * m + 4 * g + r;
-            const double v = regs ? out[m][r] : hb[R * kHbPitch + kWaveCols * wave + l];
-            const int E = erow[R];
-            const uint32_t w = E == kBadExp ? 0u : digit_word(v, E);
-            const uint32_t w0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x00, 0xF, 0xF, false);
-            const uint32_t w1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x55, 0xF, 0xF, false);
-            const uint32_t w2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0xAA, 0xF, 0xF, false);
-            const uint32_t w3 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0xFF, 0xF, 0xF, false);
-            const uint32_t x = __builtin_amdgcn_perm(w1, w0, sel);   // plane t4 of values 0, 1 of the quad
-            const uint32_t y = __builtin_amdgcn_perm(w3, w2, sel);   // of values 2, 3
-            const uint32_t d = __builtin_amdgcn_perm(y, x, 0x05040100u);
-            if (row0 + R < n) {
+            const double v = decltype(from_hb)::value ? hb[R * kHbPitch + kWaveCols * wave + l] : out[m][r];
+            const int E = Ev[m][r];
+            uint32_t w = digit_word(v, E);   // unconditional: no branch around the arithmetic
+            w = E == kBadExp ? 0u : w;
+            const uint32_t x = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x4E, 0xF, 0xF, false), w, selA);
+            const uint32_t d = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false), x, selB);
+            if (kFast) {
+              uint8_t* dst = Dn + (ubase + sm * m + sr * r + 2 * (int64_t)kTileBytes * h);
+              *(uint32_t*)(dst + (lrow + loff)) = d;
+            } else if (row0 + R < n) {
               const int64_t c2 = fibre(R);
-              const int i2 = kGroupCols * h + kWaveCols * wave + l;
-              uint8_t* dst = Dn + ((c2 >> 4) * nks2 + (i2 >> 6)) * (int64_t)kTileBytes + kPlaneBytes * t4 +
-                             16 * (16 * ((i2 >> 4) & 3) + (c2 & 15)) + 4 * (l >> 2);
-              *(uint32_t*)dst = d;
+              uint8_t* dst = Dn + (((c2 >> 4) * nks2 + 2 * h) * (int64_t)kTileBytes + 16 * (c2 & 15));
+              *(uint32_t*)(dst + loff) = d;
             }
           }
-      }
+        }
+      };
+      auto both = [&](auto fastc) __attribute__((always_inline)) {
+        if (g2 == 2) {
+          emit(std::true_type{}, fastc, 0);
+          emit(std::false_type{}, fastc, 1);
+        } else {
+          emit(std::false_type{}, fastc, 0);
+        }
+      };
+      if (fast)
+        both(std::true_type{});
+      else
+        both(std::false_type{});
       __syncthreads();   // the LDS values and exponents are rewritten by the next fibres
     }
   };
   auto end_item = [&]() __attribute__((always_inline)) {
     if (ci == nch - 1) {
-      // 2^(Ex + Ep - 12) (acc6 + acc5 2^-8 + acc4 2^-16 + acc3 2^-24 + acc2 2^-32)
-      const double sc = jb.scale[tm];
+      // 2^(Ex + Ep - 12) (acc6 + acc5 2^-8 + acc4 2^-16 + acc3 2^-24 + acc2 2^-32),
+      // without branches: a non-finite column has a NaN scale, a non-finite
+      // row a NaN high word
+      const double sc = ex == kBadExp ? __builtin_nan("") : jb.scale[tm];
+      v4i epv[4];   // exponents of this lane's matrix rows 16 m + 4 g + r
+#pragma unroll
+      for (int m = 0; m < 4; ++m) epv[m] = *(const v4i*)&pexp[pb][16 * m + 4 * g];
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int ep = pexp[pb][16 * m + 4 * g + r];
+          const int ep = epv[m][r];
           double w = (double)acc[0][m][r] * 0x1p-32;
           w = fma((double)acc[1][m][r], 0x1p-24, w);
           w = fma((double)acc[2][m][r], 0x1p-16, w);
           w = fma((double)acc[3][m][r], 0x1p-8, w);
           w += (double)acc[4][m][r];
-          w = (ex == kBadExp || ep == kBadExp) ? __builtin_nan("") : ldexp(w, ex + ep - 12);
+          w = ldexp(w, ex + ep - 12);
+          w = __hiloint2double(ep == kBadExp ? 0x7FF80000 : __double2hiint(w), __double2loint(w));
           out[m][r] = fma(sc, w, out[m][r]);
           if (SWAP) __builtin_amdgcn_sched_barrier(0);   // one output at a time (registers)
         }
@@ -534,7 +590,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         for (int m = 0; m < 4; ++m) acc[o][m] = v4i{0, 0, 0, 0};
       if (tm == nterms - 1) {   // the group's outputs are complete
         if constexpr (FUSE) {
-          fused_digits(q);
+          fused_digits();
         } else if (ca < nfib) {
           double* __restrict__ Y = (double*)jb.Y;
           const double* __restrict__ base = (const double*)jb.base;

@@ -183,6 +183,10 @@ int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, i
   for (int o = 0; o < nouts; ++o) nchains += outs[o].nterms;
   const size_t slot = prec == SETD_PREC_I8X4 ? i8_slot_bytes(d, dims) : 0;
   auto fusable = [](int m) { return m == 128 || m == 256; };
+  // SETD_I8_EMIT=0 makes every product write its FP64 result and the next one
+  // slice it (same order of the modes): the emitted digits must equal these
+  const char* emit_env = std::getenv("SETD_I8_EMIT");
+  const bool emit = emit_env == nullptr || emit_env[0] != '0';
   // I8X4, d = 3, n1 and n2 in {128, 256}, n3 <= 256: the products run in the
   // order 3, 1, 2 (the modes commute), so that both intermediates are emitted
   // as digits by the product before them: mode 3 writes the mode-1 digits
@@ -194,32 +198,36 @@ int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, i
     auto slotA = [&](int c) { return (void*)(base_ws + (size_t)c * slot); };
     auto slotB = [&](int c) { return (void*)(base_ws + (size_t)(nchains + c) * slot); };
     LaunchKind k3{false, prec, DType::F64, base_ws + (size_t)2 * nchains * slot, i8bytes - (size_t)2 * nchains * slot};
-    k3.fuse_next = dims[0];
+    k3.fuse_next = emit ? dims[0] : 0;
     LaunchKind k1{true, prec, DType::F64, i8ws, i8bytes};
-    k1.presliced = true;
-    k1.fuse_next = dims[1];
+    k1.presliced = emit;
+    k1.fuse_next = emit ? dims[1] : 0;
     LaunchKind k2{false, prec, DType::F64, i8ws, i8bytes};
-    k2.presliced = true;
+    k2.presliced = emit;
     ModeJobs J;
     J.njobs = 0;
     int c = 0;
     for (int o = 0; o < nouts; ++o)
-      for (int t = 0; t < outs[o].nterms; ++t, ++c)
-        SETD_TRY(push(J, mk_job(outs[o].term[t].X, outs[o].term[t].P[2], 1.0, slotA(c), nullptr,
-                                (int64_t)dims[0] * dims[1], dims[2], 1), k3, s));
+      for (int t = 0; t < outs[o].nterms; ++t, ++c) {
+        const TuckerTerm& tm = outs[o].term[t];
+        SETD_TRY(push(J, mk_job(tm.X, tm.P[2], 1.0, emit ? slotA(c) : tm.Y1, nullptr, (int64_t)dims[0] * dims[1],
+                                dims[2], 1), k3, s));
+      }
     SETD_TRY(flush(J, k3, s));
     c = 0;
     for (int o = 0; o < nouts; ++o)
-      for (int t = 0; t < outs[o].nterms; ++t, ++c)
-        SETD_TRY(push(J, mk_job(slotA(c), outs[o].term[t].P[0], 1.0, slotB(c), nullptr, 1, dims[0],
+      for (int t = 0; t < outs[o].nterms; ++t, ++c) {
+        const TuckerTerm& tm = outs[o].term[t];
+        SETD_TRY(push(J, mk_job(emit ? slotA(c) : tm.Y1, tm.P[0], 1.0, emit ? slotB(c) : tm.Y2, nullptr, 1, dims[0],
                                 (int64_t)dims[1] * dims[2]), k1, s));
+      }
     SETD_TRY(flush(J, k1, s));
     c = 0;
     for (int o = 0; o < nouts; ++o) {
       ModeJob jb{};
       jb.nterms = outs[o].nterms;
       for (int t = 0; t < outs[o].nterms; ++t, ++c) {
-        jb.X[t] = slotB(c);
+        jb.X[t] = emit ? slotB(c) : outs[o].term[t].Y2;
         jb.P[t] = outs[o].term[t].P[1];
         jb.scale[t] = outs[o].term[t].scale;
       }
@@ -236,7 +244,7 @@ int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, i
   // I8X4 with n1 <= 256 and n2 in {128, 256}: the mode-1 products emit the
   // mode-2 digits straight into one buffer per chain (the first slots of the
   // workspace; the slicing passes get the rest), and mode 2 reads them
-  const bool fuse = prec == SETD_PREC_I8X4 && d >= 2 && dims[0] <= 256 && (dims[1] == 128 || dims[1] == 256) &&
+  const bool fuse = emit && prec == SETD_PREC_I8X4 && d >= 2 && dims[0] <= 256 && (dims[1] == 128 || dims[1] == 256) &&
                     (size_t)(nchains + 1) * slot <= i8bytes;
   char* chain_digits = (char*)i8ws;
   auto chain_slot = [&](int chain) { return (void*)(chain_digits + (size_t)chain * slot); };
