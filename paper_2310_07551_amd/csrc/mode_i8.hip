@@ -157,10 +157,12 @@ __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
 // X[a + na p + na n b].  The buffer is tiled the way the matrix cores read
 // it: tile (c / 16, p / 64) of kTileBytes at ((c / 16) (ldp / 64) + p / 64)
 // kTileBytes holds digit plane s at s kPlaneBytes, and there the 16 bytes of
-// lane 16 ((p / 16) % 4) + c % 16: the digits of values p / 16 16 .. + 15 of
+// slot 4 (c % 16) + (p / 16) % 4: the digits of values p / 16 16 .. + 15 of
 // fibre c.  One load instruction of a wave thus reads 1 KB of contiguous
-// memory.  After the tiles of round_up(fibres, 16) fibres: one int32
-// exponent per fibre.
+// memory (lane (g, l) takes slot 4 l + g), and a fibre's 64 values of a plane
+// are 64 contiguous bytes, so a product that emits the digits of a few
+// fibres writes whole 64-byte sectors.  After the tiles of
+// round_up(fibres, 16) fibres: one int32 exponent per fibre.
 // A workgroup slices 32 fibres that are consecutive in the digit buffer, 256
 // values at a time, each thread 32 values of one fibre.  The digit planes are
 // assembled in LDS and leave as whole fibre rows (1 KB per fibre and chunk),
@@ -258,10 +260,10 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
     for (int e = tid; e < kSliceCols * kw / 4; e += 256) {
       const int ln = e & 63, sp = (e >> 6) & 3, rest = e >> 8;
       const int cbl = rest / ksc, ks = rest - cbl * ksc;
-      const int pcw = 16 * cbl + (ln & 15), gg = ln >> 4;
+      const int pcw = 16 * cbl + (ln >> 2), gg = ln & 3;
       if (pcw >= nv) continue;
       const int64_t f = fib0 + pcw;
-      uint8_t* dst = D + (((f >> 4) * nks + kc / 64 + ks) * 4 + sp) * (int64_t)kPlaneBytes + 16 * (16 * gg + (f & 15));
+      uint8_t* dst = D + (((f >> 4) * nks + kc / 64 + ks) * 4 + sp) * (int64_t)kPlaneBytes + 16 * (4 * (f & 15) + gg);
       *(v4i*)dst = *(const v4i*)(stage + pcw * kStageRow + 64 * (4 * ks + gg) + 16 * sp);
     }
     __syncthreads();   // the stage is rewritten by the next chunk
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     column(p, ca, fib);
     const uint8_t* D = (const uint8_t*)jb.X[p.tm];
     const int64_t f = ca < nfib ? fib : 0;
-    return D + ((f >> 4) * (ldp / 64) + (p.ci * kPanelK + k64) / 64) * (int64_t)kTileBytes + 16 * (16 * g + (f & 15));
+    return D + ((f >> 4) * (ldp / 64) + (p.ci * kPanelK + k64) / 64) * (int64_t)kTileBytes + 16 * (4 * (f & 15) + g);
   };
   // panel of item i: thread tid holds 16-byte unit `lane` of rows wave + 8 r
   v4i pn[8];
@@ -495,10 +497,11 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       const uint32_t selA = t4 < 2 ? 0x05040100u : 0x03020706u;    // keep 2 own bytes, take 2 of lane ^ 2
       const uint32_t selB = (t4 & 1) ? 0x03070105u : 0x06020400u;  // interleave with lane ^ 1
       // Destination of value (R, i2): tile (c2 / 16) nks2 + i2 / 64, plane t4,
-      // lane slot 16 ((i2 / 16) % 4) + c2 % 16, byte 4 (l / 4); with
-      // i2 = 128 h + 16 wave + l the column part is the same for every row.
-      const uint32_t loff = (uint32_t)((wave >> 2) * kTileBytes + kPlaneBytes * t4 + 256 * (wave & 3) + 4 * (l >> 2));
-      // Row part ((c2 / 16) nks2) kTileBytes + 16 (c2 % 16) = ubase + sm m + sr r + lrow
+      // slot 4 (c2 % 16) + (i2 / 16) % 4, byte 4 (l / 4); with
+      // i2 = 128 h + 16 wave + l the column part is the same for every row,
+      // and the four waves with the same wave / 4 fill a fibre's 64 bytes.
+      const uint32_t loff = (uint32_t)((wave >> 2) * kTileBytes + kPlaneBytes * t4 + 16 * (wave & 3) + 4 * (l >> 2));
+      // Row part ((c2 / 16) nks2) kTileBytes + 64 (c2 % 16) = ubase + sm m + sr r + lrow
       // when the rows come in whole blocks of 16 (n % 16 == 0) whose fibres are
       // evenly spaced (a multiple of 16 apart for modes >= 2, consecutive from a
       // multiple of 16 for mode 1).
@@ -510,13 +513,13 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         fast = n % 16 == 0;
         ubase = ((row0 + (int64_t)n * set) >> 4) * tstride;
         sm = tstride;
-        sr = 16;
-        lrow = 64 * g;
+        sr = 64;
+        lrow = 256 * g;
       } else {
         const int64_t fs = fstride >> 4;
         sr = fs * tstride;
         fast = n % 16 == 0 && fstride % 16 == 0 && 12 * sr < ((int64_t)1 << 31);
-        ubase = ((set >> 4) + fs * (row0 + (int64_t)n * cur.bslab)) * tstride + 16 * (set & 15);
+        ubase = ((set >> 4) + fs * (row0 + (int64_t)n * cur.bslab)) * tstride + 64 * (set & 15);
         sm = 16 * sr;
         lrow = (uint32_t)(4 * g * sr);
       }
@@ -539,7 +542,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
               *(uint32_t*)(dst + (lrow + loff)) = d;
             } else if (row0 + R < n) {
               const int64_t c2 = fibre(R);
-              uint8_t* dst = Dn + (((c2 >> 4) * nks2 + 2 * h) * (int64_t)kTileBytes + 16 * (c2 & 15));
+              uint8_t* dst = Dn + (((c2 >> 4) * nks2 + 2 * h) * (int64_t)kTileBytes + 64 * (c2 & 15));
               *(uint32_t*)(dst + loff) = d;
             }
           }
