@@ -310,15 +310,15 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   // FUSE, modes >= 2: next-mode fibres per row of this product (one division per workgroup)
   const int64_t fstride = FUSE && !MODE1 ? na / nnext : 0;
 
-  // Position of an item in the run: group q (column group ct of slab
-  // bslab), term tm, contraction chunk ci.  Items advance incrementally: a
+  // Position of an item in the run: column group ct of slab bslab, term tm,
+  // contraction chunk ci.  Items advance incrementally: a
   // 64-bit division per item costs more scalar instructions than its k-steps.
   struct Pos {
-    int q, tm, ci;
+    int tm, ci;
     int64_t ct, bslab;
   };
   auto first_pos = [&]() __attribute__((always_inline)) {
-    Pos p{0, 0, 0, MODE1 ? grp0 : grp0 % jb.tiles_a, MODE1 ? 0 : grp0 / jb.tiles_a};
+    Pos p{0, 0, MODE1 ? grp0 : grp0 % jb.tiles_a, MODE1 ? 0 : grp0 / jb.tiles_a};
     return p;
   };
   auto advance = [&](Pos p) __attribute__((always_inline)) {
@@ -326,7 +326,6 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       p.ci = 0;
       if (++p.tm == nterms) {
         p.tm = 0;
-        ++p.q;
         if (++p.ct == jb.tiles_a && !MODE1) {
           p.ct = 0;
           ++p.bslab;
@@ -366,8 +365,24 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     for (int r = 0; r < 8; ++r) *(v4i*)(panel[buf] + (wave + 8 * r) * kPanelRow + 16 * lane) = pn[r];
     if (tid < kPanelRows) pexp[buf][tid] = pen;
   };
-  auto same_panel = [&](const Pos& a, const Pos& b) __attribute__((always_inline)) {   // always, without SWAP
-    return !SWAP || (a.tm == b.tm && a.ci == b.ci);
+  // SWAP: the next item's panel goes into the idle buffer while the current
+  // item runs, rows 2 j and 2 j + 1 of every thread's eight at k-step j (the
+  // loads are issued before that step's products and stored after them); the
+  // units past the chunk's width are never read, so their lanes load a valid
+  // address and store whatever it holds
+  v4i pq[2];
+  auto fetch_rows = [&](const Pos& p, int r0) __attribute__((always_inline)) {
+    const uint8_t* P = (const uint8_t*)jb.P[p.tm];
+    const int kc = p.ci * kPanelK;
+    const int units = (ldp - kc < kPanelK ? ldp - kc : kPanelK) / 4;
+    const int u = lane < units ? lane : 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      pq[h] = *(const v4i*)(P + (int64_t)(row0 + wave + 8 * (r0 + h)) * rowbytes + 4 * kc + 16 * u);
+  };
+  auto store_rows = [&](int buf, int r0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) *(v4i*)(panel[buf] + (wave + 8 * (r0 + h)) * kPanelRow + 16 * lane) = pq[h];
   };
 
   fetch_panel(first_pos());
@@ -387,13 +402,13 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     for (int m = 0; m < 4; ++m) acc[o][m] = v4i{0, 0, 0, 0};
 
   // state of the current item
-  int i = 0, q = 0, tm = 0, ci = 0, kend = 0, ex = 0;
+  int i = 0, tm = 0, ci = 0, kend = 0, ex = 0;
   Pos cur = first_pos(), nxt = cur;
+  auto nxt_pos = [&]() __attribute__((always_inline)) -> const Pos& { return nxt; };
   int64_t ca = 0, fib = 0;
   const uint8_t* bcur = nullptr;
   const uint8_t* bnext = nullptr;
   auto begin_item = [&]() __attribute__((always_inline)) {
-    q = cur.q;
     tm = cur.tm;
     ci = cur.ci;
     column(cur, ca, fib);
@@ -405,6 +420,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     ex = ((const int*)((const uint8_t*)jb.X[tm] + ntot16 * rowbytes))[ca < nfib ? fib : 0];
     bcur = bptr(cur, 0);
     bnext = i + 1 < nitems ? bptr(nxt, 0) : bcur;   // after the last item: a harmless reload
+    if constexpr (SWAP) pen = ((const int*)((const uint8_t*)jb.P[nxt.tm] + rowbytes * ldp))[row0 + (tid & 63)];
   };
   // FUSE (one term, n <= 256; the next mode's size nnext in {128, 256}):
   // instead of the FP64 product, the digit planes of the operand of the next
@@ -640,11 +656,14 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
           for (int r = 0; r < 4; ++r) out[m][r] = 0.0;
       }
     }
-    if (i + 1 < nitems && !same_panel(cur, nxt)) {
-      // every wave is past its reads of panel[pb ^ 1] (an earlier item's)
-      fetch_panel(nxt);
-      store_panel(pb ^ 1);
-      __syncthreads();
+    if (SWAP && i + 1 < nitems) {
+      // the rows the item's k-steps did not fetch (items shorter than 4 k-steps)
+      for (int r0 = 2 * ((kend + 63) / 64); r0 < 8; r0 += 2) {
+        fetch_rows(nxt, r0);
+        store_rows(pb ^ 1, r0);
+      }
+      if (tid < kPanelRows) pexp[pb ^ 1][tid] = pen;
+      __syncthreads();   // the next panel is complete; every wave is past this item's reads
       pb ^= 1;
     }
   };
@@ -709,9 +728,11 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   auto run_any = [&]() __attribute__((always_inline)) {
     v4i bA[4], bB[4];
     auto kstep = [&](int k64, v4i (&cur)[4], v4i (&nxt)[4]) {
+      if constexpr (SWAP) fetch_rows(nxt_pos(), k64 / 32);
       load4(k64 + 64 < kend ? bcur + kTileBytes * ((k64 + 64) / 64) : bnext, nxt);
       __builtin_amdgcn_sched_barrier(0);
       products(k64, cur);
+      if constexpr (SWAP) store_rows(pb ^ 1, k64 / 32);
     };
     begin_item();
     load4(bcur, bA);
