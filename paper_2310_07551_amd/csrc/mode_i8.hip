@@ -282,7 +282,10 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
 // during the current item into the second LDS buffer (SWAP; the host picks
 // it when some job has several terms or n > 256).  Without SWAP the panel is
 // loaded once and the loop has no barrier at all.
-template <bool MODE1, bool SWAP, bool FUSE>
+// FUSE: 0 = FP64 outputs; 1 = the next mode's digits, any shape; 2 = the same
+// when every row block's fibres are evenly spaced (the host checks: n % 16 == 0,
+// and for modes >= 2 na / nnext % 16 == 0), with row-block addressing only.
+template <bool MODE1, bool SWAP, int FUSE>
 __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64_t per_xcd, int sup, int nnext) {
   __shared__ __attribute__((aligned(16))) uint8_t panel[2][kPanelRows * kPanelRow];
   __shared__ __attribute__((aligned(16))) int pexp[2][kPanelRows];
@@ -517,16 +520,14 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       // i2 = 128 h + 16 wave + l the column part is the same for every row,
       // and the four waves with the same wave / 4 fill a fibre's 64 bytes.
       const uint32_t loff = (uint32_t)((wave >> 2) * kTileBytes + kPlaneBytes * t4 + 16 * (wave & 3) + 4 * (l >> 2));
-      // Row part ((c2 / 16) nks2) kTileBytes + 64 (c2 % 16) = ubase + sm m + sr r + lrow
-      // when the rows come in whole blocks of 16 (n % 16 == 0) whose fibres are
-      // evenly spaced (a multiple of 16 apart for modes >= 2, consecutive from a
+      // FUSE == 2: row part ((c2 / 16) nks2) kTileBytes + 64 (c2 % 16) =
+      // ubase + sm m + sr r + lrow (the rows come in whole blocks of 16 whose
+      // fibres are a multiple of 16 apart for modes >= 2, consecutive from a
       // multiple of 16 for mode 1).
       const int64_t tstride = (int64_t)nks2 * kTileBytes;
       int64_t ubase = 0, sm = 0, sr = 0;
       uint32_t lrow = 0;
-      bool fast;
       if constexpr (MODE1) {
-        fast = n % 16 == 0;
         ubase = ((row0 + (int64_t)n * set) >> 4) * tstride;
         sm = tstride;
         sr = 64;
@@ -534,48 +535,53 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       } else {
         const int64_t fs = fstride >> 4;
         sr = fs * tstride;
-        fast = n % 16 == 0 && fstride % 16 == 0 && 12 * sr < ((int64_t)1 << 31);
         ubase = ((set >> 4) + fs * (row0 + (int64_t)n * cur.bslab)) * tstride + 64 * (set & 15);
         sm = 16 * sr;
         lrow = (uint32_t)(4 * g * sr);
       }
-      auto emit = [&](auto from_hb, auto fastc, int h) __attribute__((always_inline)) {
-        constexpr bool kFast = decltype(fastc)::value;
+      // one row block at a time, its four rows side by side (independent
+      // operations between each write and the lane exchange that reads it)
+      auto emit = [&](auto from_hb, int h) __attribute__((always_inline)) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          if (kFast && row0 + 16 * m >= n) break;   // whole row blocks
+          if (FUSE == 2 && row0 + 16 * m >= n) break;   // whole row blocks
+          uint32_t w[4], x[4], d[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int R = 16 * m + 4 * g + r;
-            const double v = decltype(from_hb)::value ? hb[R * kHbPitch + kWaveCols * wave + l] : out[m][r];
+            const double v = decltype(from_hb)::value ? hb[(16 * m + 4 * g + r) * kHbPitch + kWaveCols * wave + l]
+                                                      : out[m][r];
             const int E = Ev[m][r];
-            uint32_t w = digit_word(v, E);   // unconditional: no branch around the arithmetic
-            w = E == kBadExp ? 0u : w;
-            const uint32_t x = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x4E, 0xF, 0xF, false), w, selA);
-            const uint32_t d = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false), x, selB);
-            if (kFast) {
+            w[r] = digit_word(v, E);   // unconditional: no branch around the arithmetic
+            w[r] = E == kBadExp ? 0u : w[r];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            x[r] = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)w[r], 0x4E, 0xF, 0xF, false), w[r], selA);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            d[r] = __builtin_amdgcn_perm((uint32_t)__builtin_amdgcn_mov_dpp((int)x[r], 0xB1, 0xF, 0xF, false), x[r], selB);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if constexpr (FUSE == 2) {
               uint8_t* dst = Dn + (ubase + sm * m + sr * r + 2 * (int64_t)kTileBytes * h);
-              *(uint32_t*)(dst + (lrow + loff)) = d;
-            } else if (row0 + R < n) {
-              const int64_t c2 = fibre(R);
-              uint8_t* dst = Dn + (((c2 >> 4) * nks2 + 2 * h) * (int64_t)kTileBytes + 64 * (c2 & 15));
-              *(uint32_t*)(dst + loff) = d;
+              *(uint32_t*)(dst + (lrow + loff)) = d[r];
+            } else {
+              const int R = 16 * m + 4 * g + r;
+              if (row0 + R < n) {
+                const int64_t c2 = fibre(R);
+                uint8_t* dst = Dn + (((c2 >> 4) * nks2 + 2 * h) * (int64_t)kTileBytes + 64 * (c2 & 15));
+                *(uint32_t*)(dst + loff) = d[r];
+              }
             }
           }
         }
       };
-      auto both = [&](auto fastc) __attribute__((always_inline)) {
-        if (g2 == 2) {
-          emit(std::true_type{}, fastc, 0);
-          emit(std::false_type{}, fastc, 1);
-        } else {
-          emit(std::false_type{}, fastc, 0);
-        }
-      };
-      if (fast)
-        both(std::true_type{});
-      else
-        both(std::false_type{});
+      if (g2 == 2) {
+        emit(std::true_type{}, 0);
+        emit(std::false_type{}, 1);
+      } else {
+        emit(std::false_type{}, 0);
+      }
       __syncthreads();   // the LDS values and exponents are rewritten by the next fibres
     }
   };
@@ -815,9 +821,17 @@ int launch_gemm_i8(const ModeJobs& J, bool mode1, hipStream_t s, int fuse_next) 
   for (int j = 0; j < G.njobs; ++j) swap = swap || G.job[j].nterms > 1 || G.job[j].n > kPanelK;
   const int64_t pxcd = ceil_div(tot, 8);
   const dim3 grid((unsigned)(pxcd * 8));
-  auto kern = fuse_next ? (mode1 ? gemm_i8_kernel<true, false, true> : gemm_i8_kernel<false, false, true>)
-             : mode1     ? (swap ? gemm_i8_kernel<true, true, false> : gemm_i8_kernel<true, false, false>)
-                         : (swap ? gemm_i8_kernel<false, true, false> : gemm_i8_kernel<false, false, false>);
+  // the fused form with row-block addressing when every job allows it
+  bool aligned = true;
+  for (int j = 0; j < G.njobs && fuse_next; ++j) {
+    const ModeJob& jb = G.job[j];
+    const int64_t fs = mode1 ? 0 : jb.na / fuse_next;
+    aligned = aligned && jb.n % 16 == 0 && fs % 16 == 0 && 768 * fs * fuse_next < ((int64_t)1 << 31);
+  }
+  auto kern = fuse_next ? (aligned ? (mode1 ? gemm_i8_kernel<true, false, 2> : gemm_i8_kernel<false, false, 2>)
+                                   : (mode1 ? gemm_i8_kernel<true, false, 1> : gemm_i8_kernel<false, false, 1>))
+             : mode1     ? (swap ? gemm_i8_kernel<true, true, 0> : gemm_i8_kernel<true, false, 0>)
+                         : (swap ? gemm_i8_kernel<false, true, 0> : gemm_i8_kernel<false, false, 0>);
   hipLaunchKernelGGL(kern, grid, dim3(512), 0, s, G, pxcd, sup, fuse_next);
   SETD_LAUNCHED();
   return SETD_OK;
