@@ -90,6 +90,19 @@ __device__ __forceinline__ int exp_above(double m) {
   return e;
 }
 
+// Magnitude key of x: its high word without the sign.  Over finite values
+// the exponent field (key >> 20) grows with |x|; inf and NaN have field 0x7FF.
+__device__ __forceinline__ int mag_key(double x) { return __double2hiint(x) & 0x7FFFFFFF; }
+
+// Exponent of a tensor fibre from the largest magnitude key k of its entries:
+// the frexp exponent of the largest entry (field - 1022) when that entry is
+// normal, -1022 when every entry is zero or subnormal (|x| < 2^-1022), and
+// kBadExp when some entry is not finite.  |x| < 2^E for every entry.
+__device__ __forceinline__ int fibre_exp(int k) {
+  const int f = k >> 20;
+  return f == 0x7FF ? kBadExp : (f == 0 ? -1022 : f - 1022);
+}
+
 // The four digits of x (|x| < 2^E) as the bytes of one word, t0 lowest:
 // w = q + 0x808080 has bytes b0, b1, b2 (unsigned) and a signed top byte
 // with q = sum_{k<3} (b_k - 128) 2^(8k) + t3 2^24; b_k - 128 as a signed
@@ -171,7 +184,7 @@ __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
 template <bool MODE1>
 __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t per_xcd) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kSliceCols * kStageRow];
-  __shared__ double red[8][kSliceCols];
+  __shared__ int red[8][kSliceCols];
   __shared__ int colexp[kSliceCols];
   const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;   // uniform over the block
@@ -212,22 +225,19 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
       for (int j = 0; j < 32; ++j) v[j] = (ok && k0 + j < n) ? p[step * j] : 0.0;
     }
   };
-  // the fibre's largest magnitude (z = sum of 0 * v: NaN iff some value is not finite)
-  double m = 0.0, z = 0.0;
+  // the fibre's largest magnitude key
+  int mk = 0;
   for (int kc = 0; kc < n; kc += kSliceChunk) {
     load(kc);
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      z = fma(0.0, v[j], z);
-      m = fmax(m, fabs(v[j]));
-    }
+    for (int j = 0; j < 32; ++j) mk = max(mk, mag_key(v[j]));
   }
-  red[ps][pc] = z != z ? __builtin_inf() : m;
+  red[ps][pc] = mk;
   __syncthreads();
   if (tid < kSliceCols) {
-    double mm = red[0][tid];
-    for (int q = 1; q < 8; ++q) mm = fmax(mm, red[q][tid]);
-    const int e = isfinite(mm) ? exp_above(mm) : kBadExp;
+    int mm = red[0][tid];
+    for (int q = 1; q < 8; ++q) mm = max(mm, red[q][tid]);
+    const int e = fibre_exp(mm);
     colexp[tid] = e;
     if (tid < nv) Dexp[fib0 + tid] = e;
   }
@@ -289,7 +299,7 @@ template <bool MODE1, bool SWAP, int FUSE>
 __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64_t per_xcd, int sup, int nnext) {
   __shared__ __attribute__((aligned(16))) uint8_t panel[2][kPanelRows * kPanelRow];
   __shared__ __attribute__((aligned(16))) int pexp[2][kPanelRows];
-  __shared__ int emax[FUSE ? 2 : 1][kGemmWaves][kPanelRows];   // FUSE: biased exponent maxima per half, wave, row
+  __shared__ int emax[FUSE ? 2 : 1][kGemmWaves][kPanelRows];   // FUSE: magnitude-key maxima per half, wave, row
   __shared__ __attribute__((aligned(16))) int erow[kPanelRows];
   const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
   if (t >= J.total_tiles) return;   // uniform over the block
@@ -433,13 +443,12 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   // i1, the whole mode-2 fibre i1 + n1 i3.  Modes >= 2 (the next mode is 1):
   // column a is (i1, a / n1), and the groups sharing a / n1 hold, for each
   // row i and slab b, the whole mode-1 fibre a / n1 + (na / n1)(i + n b).
-  // The first group's values wait
-  // in LDS (the second panel buffer, unused without SWAP); at the last group
-  // the fibre exponents (the maximum over both groups of the frexp exponent
-  // of every value, reduced across lanes as packed 16-bit fields: zero -> 0,
-  // non-finite -> the largest) are formed and every value is cut into its
-  // digits exactly as the slicing kernel would, a quad of lanes trading bytes
-  // so that each lane stores one 4-byte run of one plane.
+  // The first group's values wait in LDS (the second panel buffer, unused
+  // without SWAP); at the last group the fibre exponents are formed from the
+  // largest magnitude key over both groups (reduced across lanes with DPP,
+  // then across waves in LDS) and every value is cut into its digits exactly
+  // as the slicing kernel would, a quad of lanes trading bytes so that each
+  // lane stores one 4-byte run of one plane.
   auto fused_digits = [&]() __attribute__((always_inline)) {
     if constexpr (FUSE) {
       const int g2 = nnext / kGroupCols;
@@ -450,31 +459,18 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         return MODE1 ? row0 + R + (int64_t)n * set : set + fstride * (row0 + R + (int64_t)n * cur.bslab);
       };
       double* hb = (double*)panel[1];   // [64 rows][kHbPitch] first-group values
-      typedef unsigned short us2 __attribute__((ext_vector_type(2)));
-      union U2 {
-        us2 v;
-        int i;
-      };
-      U2 pk[8];   // biased exponents of this lane's 16 values, two to a word
+      int hk[4][4];   // magnitude keys of this lane's 16 values
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double v = out[m][r];
-          int e = 0;
-          (void)frexp(v, &e);
-          const unsigned short be = v == 0.0 ? 0 : (isfinite(v) ? (unsigned short)(e + 2048) : (unsigned short)0xFFFF);
-          pk[2 * m + (r >> 1)].v[r & 1] = be;
-        }
+        for (int r = 0; r < 4; ++r) hk[m][r] = mag_key(out[m][r]);
       // maximum over the 16 lanes of a row block: swaps within quads, then
       // the half-row and row mirrors (DPP, no LDS traffic)
       auto lane_max = [&](auto ctrl) __attribute__((always_inline)) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          U2 o;
-          o.i = __builtin_amdgcn_mov_dpp(pk[k].i, decltype(ctrl)::value, 0xF, 0xF, false);
-          pk[k].v = __builtin_elementwise_max(pk[k].v, o.v);
-        }
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) hk[m][r] = max(hk[m][r], __builtin_amdgcn_mov_dpp(hk[m][r], decltype(ctrl)::value, 0xF, 0xF, true));
       };
       lane_max(std::integral_constant<int, 0xB1>{});    // quad_perm [1, 0, 3, 2]
       lane_max(std::integral_constant<int, 0x4E>{});    // quad_perm [2, 3, 0, 1]
@@ -484,7 +480,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) emax[half][wave][16 * m + 4 * g + r] = pk[2 * m + (r >> 1)].v[r & 1];
+          for (int r = 0; r < 4; ++r) emax[half][wave][16 * m + 4 * g + r] = hk[m][r];
       if (half != g2 - 1) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -500,7 +496,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
         int bmax = 0;
         for (int h = 0; h < g2; ++h)
           for (int w = 0; w < kGemmWaves; ++w) bmax = max(bmax, emax[h][w][tid]);
-        const int E = bmax == 0 ? 0 : (bmax == 0xFFFF ? kBadExp : bmax - 2048);
+        const int E = fibre_exp(bmax);
         erow[tid] = E;
         if (row0 + tid < n) {
           ((int*)(Dn + ((ntot2 + 15) & ~(int64_t)15) * 4 * (int64_t)ldp2))[fibre(tid)] = E;
