@@ -482,6 +482,10 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
 #pragma unroll
           for (int r = 0; r < 4; ++r) emax[half][wave][16 * m + 4 * g + r] = hk[m][r];
       if (half != g2 - 1) {
+        // every wave is past its reads of the previous set's values (its
+        // digits); waiting here rather than after them lets a wave that has
+        // cut its digits start the next products while others still cut
+        __syncthreads();
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -578,7 +582,11 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       } else {
         emit(std::false_type{}, 0);
       }
-      __syncthreads();   // the LDS values and exponents are rewritten by the next fibres
+      // No barrier after the digits: the next set's first-group values wait
+      // for the barrier above; its lane maxima overwrite emax only once their
+      // writer is past this set's second barrier (the reduction that read them
+      // is done), and erow is rewritten only after the next set's first
+      // barrier, which every wave reaches after cutting these digits.
     }
   };
   auto end_item = [&]() __attribute__((always_inline)) {
