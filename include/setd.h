@@ -66,7 +66,9 @@ extern "C" {
                                   2^-29 of |x|max |p|max per product term);
                                   FP64 inputs, outputs and sums; intermediates
                                   kept as digits where the next product can
-                                  take them so                               */
+                                  take them so (bit-identical to slicing the
+                                  FP64 intermediate; the environment variable
+                                  SETD_I8_EMIT=0 turns this off, for tests)  */
 
 /* ---- reaction terms g (eq. twocompdisc: two components u, v) ---- */
 #define SETD_G_NONE         0  /* g = 0; nparams = 0                            */
