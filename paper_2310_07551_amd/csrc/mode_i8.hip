@@ -210,6 +210,11 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
   uint8_t* __restrict__ D = (uint8_t*)jb.Y;
   int* __restrict__ Dexp = (int*)(D + ((ntot + 15) & ~(int64_t)15) * 4 * (int64_t)ldp);
   double v[32];
+  // modes >= 2, a whole chunk of 32 fibres: value j of every thread at a
+  // workgroup-uniform address plus a 32-bit lane offset (no per-value address
+  // arithmetic, no branches); otherwise clamped addresses and a select
+  const bool whole = !MODE1 && nv == kSliceCols && na <= ((int64_t)1 << 21);
+  const uint32_t lane_off = (uint32_t)((pc + na * 32 * ps) * 8);
   auto load = [&](int kc) {
     const int k0 = kc + 32 * ps;
     if (MODE1 && ok && (n % 2 == 0) && k0 + 32 <= n) {
@@ -219,10 +224,17 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
         v[j] = w[0];
         v[j + 1] = w[1];
       }
-    } else {
-      const double* p = src + step * k0;
+    } else if (whole && kc + kSliceChunk <= n) {
+      const char* ub = (const char*)(X + fa0 + na * (int64_t)n * bslab + na * (int64_t)kc);
 #pragma unroll
-      for (int j = 0; j < 32; ++j) v[j] = (ok && k0 + j < n) ? p[step * j] : 0.0;
+      for (int j = 0; j < 32; ++j) v[j] = *(const double*)(ub + na * 8 * j + lane_off);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        const bool in = ok && k0 + j < n;
+        const double x = src[step * (in ? k0 + j : 0)];
+        v[j] = in ? x : 0.0;
+      }
     }
   };
   // the fibre's largest magnitude key
@@ -256,7 +268,10 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
       for (int q = 0; q < 4; ++q) {
         uint32_t w[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) w[e] = finite ? digit_word(v[16 * h + 4 * q + e], E) : 0u;
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t x = digit_word(v[16 * h + 4 * q + e], E);   // unconditional: no branch
+          w[e] = finite ? x : 0u;
+        }
         digit_planes(w[0], w[1], w[2], w[3], d[q]);
       }
       uint8_t* o = stage + pc * kStageRow + 64 * run;
@@ -265,16 +280,22 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
         *(v4i*)(o + 16 * sp) = v4i{(int)d[0][sp], (int)d[1][sp], (int)d[2][sp], (int)d[3][sp]};
     }
     __syncthreads();
-    // 16-byte units in tile order: (local block of 16 fibres, k-step, plane, lane)
+    // 16-byte units in tile order: (local block of 16 fibres, k-step, plane,
+    // slot); unit e = tid + 256 it has slot tid % 64, plane tid / 64 and
+    // (block, k-step) = (it / ksc, it % ksc), the latter kept incrementally
     const int nks = ldp / 64, ksc = kw / 64;
-    for (int e = tid; e < kSliceCols * kw / 4; e += 256) {
-      const int ln = e & 63, sp = (e >> 6) & 3, rest = e >> 8;
-      const int cbl = rest / ksc, ks = rest - cbl * ksc;
+    const int ln = tid & 63, sp = tid >> 6;
+    for (int it = 0, cbl = 0, ks = 0; it < kSliceCols * kw / 1024; ++it) {
       const int pcw = 16 * cbl + (ln >> 2), gg = ln & 3;
-      if (pcw >= nv) continue;
-      const int64_t f = fib0 + pcw;
-      uint8_t* dst = D + (((f >> 4) * nks + kc / 64 + ks) * 4 + sp) * (int64_t)kPlaneBytes + 16 * (4 * (f & 15) + gg);
-      *(v4i*)dst = *(const v4i*)(stage + pcw * kStageRow + 64 * (4 * ks + gg) + 16 * sp);
+      if (pcw < nv) {
+        const int64_t f = fib0 + pcw;
+        uint8_t* dst = D + (((f >> 4) * nks + kc / 64 + ks) * 4 + sp) * (int64_t)kPlaneBytes + 16 * (4 * (f & 15) + gg);
+        *(v4i*)dst = *(const v4i*)(stage + pcw * kStageRow + 64 * (4 * ks + gg) + 16 * sp);
+      }
+      if (++ks == ksc) {
+        ks = 0;
+        ++cbl;
+      }
     }
     __syncthreads();   // the stage is rewritten by the next chunk
   }
