@@ -531,11 +531,29 @@ __global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int
   }
   __syncthreads();
   constexpr int KB = 4;
-  for (int rep = 0; rep < reps; ++rep) {
-    const int64_t q = (grp * reps + rep) * kLdsWaves + wave;
-    if (q >= npairs) return;   // no barrier follows
+  const double* __restrict__ X = (const double*)jb.X[0];
+  // (a-block, slab) pair of repetition r (past the job's pairs: not run), and
+  // the lane's first X element of it
+  auto pair_of = [&](int r) { return (grp * reps + r) * kLdsWaves + wave; };
+  auto xbase = [&](int64_t q) {
     const int64_t at = q % jb.tiles_a, b = q / jb.tiles_a;
-    const int64_t a0 = at * 64, arow = a0 + 4 * l;
+    return X + na * (int64_t)n * b + at * 64 + 4 * l + na * g;
+  };
+  auto loadblk = [&](const double* xb, int p0, d4* xr) {
+#pragma unroll
+    for (int k = 0; k < KB; ++k) xr[k] = *(const d4*)(xb + na * (int64_t)(p0 + 4 * k));
+  };
+  d4 xa[KB], xq[KB];
+  if (pair_of(0) >= npairs) return;   // no barrier follows
+  const double* xb = xbase(pair_of(0));
+  loadblk(xb, 0, xa);
+  for (int rep = 0; rep < reps; ++rep) {
+    const int64_t q = pair_of(rep);
+    // the next pair's first block is loaded during this pair's last one
+    const bool next = rep + 1 < reps && pair_of(rep + 1) < npairs;
+    const double* xn = next ? xbase(pair_of(rep + 1)) : xb;
+    const int64_t at = q % jb.tiles_a, b = q / jb.tiles_a;
+    const int64_t a0 = at * 64;
     const int64_t slab = na * (int64_t)n * b;
     d4 acc[4][4];
 #pragma unroll
@@ -543,11 +561,6 @@ __global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[m][u] = d4{0.0, 0.0, 0.0, 0.0};
     {
-      const double* __restrict__ xb = (const double*)jb.X[0] + slab + arow + na * g;
-      auto loadblk = [&](int p0, d4* xr) {
-#pragma unroll
-        for (int k = 0; k < KB; ++k) xr[k] = *(const d4*)(xb + na * (int64_t)(p0 + 4 * k));
-      };
       auto mmablk = [&](int p0, const d4* xr) {
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
@@ -558,12 +571,11 @@ __global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int
             for (int m = 0; m < 4; ++m) acc[m][u] = mfma(xr[k][m], pv[u], acc[m][u]);
         }
       };
-      d4 xa[KB], xq[KB];
-      loadblk(0, xa);
       for (int p0 = 0; p0 < n; p0 += 8 * KB) {   // n % 32 == 0
-        loadblk(p0 + 4 * KB, xq);
+        loadblk(xb, p0 + 4 * KB, xq);
         mmablk(p0, xa);
-        loadblk(p0 + 8 * KB < n ? p0 + 8 * KB : p0, xa);
+        const bool last = p0 + 8 * KB >= n;
+        loadblk(last ? xn : xb + na * (int64_t)(p0 + 8 * KB), 0, xa);   // unconditional: no branch
         mmablk(p0 + 4 * KB, xq);
       }
     }
@@ -584,6 +596,8 @@ __global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int
         }
       }
     }
+    if (!next) return;
+    xb = xn;
   }
 }
 
