@@ -645,7 +645,36 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
           double* __restrict__ Y = (double*)jb.Y;
           const double* __restrict__ base = (const double*)jb.base;
           const int64_t slab = MODE1 ? 0 : na * (int64_t)n * cur.bslab;
-          auto off = [&](int ii) __attribute__((always_inline)) { return MODE1 ? ii + (int64_t)n * ca : ca + na * (int64_t)ii + slab; };
+          if (!MODE1 && row0 + kPanelRows <= n) {
+            // modes >= 2, every row inside: one per-lane offset per item plus
+            // uniform row steps (no per-row offsets held across the loop)
+            const int64_t colb = ca + slab + na * (int64_t)(row0 + 4 * g);
+            if (base) {
+#pragma unroll
+              for (int m0 = 0; m0 < 4; m0 += 2) {
+                double bv[2][4];
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) bv[m][r] = base[colb + na * (16 * (m0 + m) + r)];
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) out[m0 + m][r] = bv[m][r] + out[m0 + m][r];
+              }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) Y[colb + na * (16 * m + r)] = out[m][r];
+          } else {
+          // rows past n, or mode 1: the row terms depend on an opaque copy of
+          // the sizes, so that the compiler does not hold sixteen per-row
+          // offsets in registers across the products (they would spill)
+          int64_t nao = MODE1 ? (int64_t)n : na;
+          int nl = n - 1;
+          asm volatile("" : "+s"(nao), "+s"(nl));
+          auto off = [&](int ii) __attribute__((always_inline)) { return MODE1 ? ii + nao * ca : ca + nao * ii + slab; };
           if (base) {   // base values in flight eight at a time (rows past n read row n - 1)
 #pragma unroll
             for (int m0 = 0; m0 < 4; m0 += 2) {
@@ -655,7 +684,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                   const int ii = row0 + 16 * (m0 + m) + 4 * g + r;
-                  bv[m][r] = base[off(ii < n ? ii : n - 1)];
+                  bv[m][r] = base[off(ii < nl ? ii : nl)];
                 }
 #pragma unroll
               for (int m = 0; m < 2; ++m)
@@ -679,6 +708,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
               for (int r = 0; r < 4; ++r)
                 if (i0 + r < n) Y[off(i0 + r)] = out[m][r];
             }
+          }
           }
         }
 #pragma unroll
