@@ -71,7 +71,6 @@ constexpr int kWaveCols = 16;
 constexpr int kGroupCols = kGemmWaves * kWaveCols;   // 128 columns per workgroup
 constexpr int kPanelK = 256;
 constexpr int kPanelRow = 4 * kPanelK + 16;
-constexpr int kHbPitch = kPanelRow / 8;   // doubles per LDS row of the fused epilogue's first-group values
 #ifndef SETD_I8_WG_PER_CU
 #define SETD_I8_WG_PER_CU 12
 #endif
@@ -425,6 +424,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   __syncthreads();
 
   double out[4][4];
+  double hv[4][4];   // FUSE with two groups per fibre set: the first group's values
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -464,8 +464,8 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
   // i1, the whole mode-2 fibre i1 + n1 i3.  Modes >= 2 (the next mode is 1):
   // column a is (i1, a / n1), and the groups sharing a / n1 hold, for each
   // row i and slab b, the whole mode-1 fibre a / n1 + (na / n1)(i + n b).
-  // The first group's values wait in LDS (the second panel buffer, unused
-  // without SWAP); at the last group the fibre exponents are formed from the
+  // The first group's values wait in registers (hv); at the last group the
+  // fibre exponents are formed from the
   // largest magnitude key over both groups (reduced across lanes with DPP,
   // then across waves in LDS) and every value is cut into its digits exactly
   // as the slicing kernel would, a quad of lanes trading bytes so that each
@@ -479,7 +479,6 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       auto fibre = [&](int R) __attribute__((always_inline)) {
         return MODE1 ? row0 + R + (int64_t)n * set : set + fstride * (row0 + R + (int64_t)n * cur.bslab);
       };
-      double* hb = (double*)panel[1];   // [64 rows][kHbPitch] first-group values
       int hk[4][4];   // magnitude keys of this lane's 16 values
 #pragma unroll
       for (int m = 0; m < 4; ++m)
@@ -503,14 +502,10 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
 #pragma unroll
           for (int r = 0; r < 4; ++r) emax[half][wave][16 * m + 4 * g + r] = hk[m][r];
       if (half != g2 - 1) {
-        // every wave is past its reads of the previous set's values (its
-        // digits); waiting here rather than after them lets a wave that has
-        // cut its digits start the next products while others still cut
-        __syncthreads();
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) hb[(16 * m + 4 * g + r) * kHbPitch + kWaveCols * wave + l] = out[m][r];
+          for (int r = 0; r < 4; ++r) hv[m][r] = out[m][r];
         return;
       }
       __syncthreads();
@@ -569,7 +564,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
           uint32_t w[4], x[4], d[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const double v = decltype(from_hb)::value ? hb[(16 * m + 4 * g + r) * kHbPitch + kWaveCols * wave + l]
+            const double v = decltype(from_hb)::value ? hv[m][r]
                                                       : out[m][r];
             const int E = Ev[m][r];
             w[r] = digit_word(v, E);   // unconditional: no branch around the arithmetic
@@ -603,11 +598,11 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
       } else {
         emit(std::false_type{}, 0);
       }
-      // No barrier after the digits: the next set's first-group values wait
-      // for the barrier above; its lane maxima overwrite emax only once their
-      // writer is past this set's second barrier (the reduction that read them
-      // is done), and erow is rewritten only after the next set's first
-      // barrier, which every wave reaches after cutting these digits.
+      // No barrier after the digits: the next set's lane maxima overwrite
+      // emax only once their writer is past this set's second barrier (the
+      // reduction that read them is done), and erow is rewritten only after
+      // the next set's first barrier, which every wave reaches after cutting
+      // these digits.
     }
   };
   auto end_item = [&]() __attribute__((always_inline)) {
