@@ -71,12 +71,8 @@ constexpr int kWaveCols = 16;
 constexpr int kGroupCols = kGemmWaves * kWaveCols;   // 128 columns per workgroup
 constexpr int kPanelK = 256;
 constexpr int kPanelRow = 4 * kPanelK + 16;
-#ifndef SETD_I8_WG_PER_CU
-#define SETD_I8_WG_PER_CU 12
-#endif
 constexpr int64_t kCus = 256;
-constexpr int64_t kGemmWgPerCu = SETD_I8_WG_PER_CU;   // workgroups per compute unit a launch aims at
-constexpr int64_t kMaxSup = 16;                       // longest run of column groups
+constexpr int64_t kMaxSup = 16;   // longest run of column groups
 
 __device__ __forceinline__ v4i mfma_i8(const v4i& a, const v4i& b, const v4i& c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
@@ -841,18 +837,33 @@ namespace {
 
 // The digit GEMM of a table of jobs whose X[t] are digit buffers.
 int launch_gemm_i8(const ModeJobs& J, bool mode1, hipStream_t s, int fuse_next) {
-  // runs of `sup` column groups per workgroup, sized for about kGemmWgPerCu
-  // workgroups per compute unit over the launch
+  // each workgroup takes a run of `sup` column groups of one row panel
   ModeJobs G = J;
-  int64_t pairs = 0;
   for (int j = 0; j < G.njobs; ++j) {
     ModeJob& jb = G.job[j];
     jb.tiles_i = (int)ceil_div(jb.n, kPanelRows);
     jb.tiles_a = (int)ceil_div(mode1 ? jb.nb : jb.na, kGroupCols);
-    pairs += (int64_t)jb.tiles_i * jb.tiles_a * (mode1 ? 1 : jb.nb);
   }
-  int sup = (int)std::min<int64_t>(kMaxSup, std::max<int64_t>(1, pairs / (kCus * kGemmWgPerCu)));
-  if (fuse_next == 2 * kGroupCols) sup = (sup + 1) & ~1;   // runs of whole mode-2 fibres
+  // Run length: one 8-wave workgroup fits a CU, so the launch takes about
+  // ceil(workgroups / CUs) rounds of (sup + 1) group-times (the one: the
+  // panel fill and pipeline start of a workgroup).  The shortest such time,
+  // ties to the shorter runs; fused launches with two groups per fibre set
+  // need even runs.
+  int sup = 1;
+  double best = 0.0;
+  for (int c = 1; c <= kMaxSup; ++c) {
+    if (fuse_next == 2 * kGroupCols && (c & 1)) continue;
+    int64_t wgs = 0;
+    for (int j = 0; j < G.njobs; ++j) {
+      const ModeJob& jb = G.job[j];
+      wgs += (int64_t)jb.tiles_i * ceil_div((int64_t)jb.tiles_a * (mode1 ? 1 : jb.nb), c);
+    }
+    const double t = (double)ceil_div(wgs, kCus) * (c + 1);
+    if (best == 0.0 || t < best) {
+      best = t;
+      sup = c;
+    }
+  }
   int64_t tot = 0;
   for (int j = 0; j < G.njobs; ++j) {
     ModeJob& jb = G.job[j];
