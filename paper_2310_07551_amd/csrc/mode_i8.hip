@@ -602,6 +602,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     }
   };
   auto end_item = [&]() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_setprio(0);
     if (ci == nch - 1) {
       // 2^(Ex + Ep - 12) (acc6 + acc5 2^-8 + acc4 2^-16 + acc3 2^-24 + acc2 2^-32),
       // without branches: a non-finite column has a NaN scale, a non-finite
@@ -762,6 +763,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
 #pragma unroll
     for (int s = 0; s + 1 < K; ++s) load4(bcur + kTileBytes * s, bb[s]);
     for (;;) {
+      __builtin_amdgcn_s_setprio(1);   // products first when a SIMD has a wave in its epilogue
 #pragma unroll
       for (int s = 0; s < K; ++s) {
         const int t = s + K - 1;
@@ -789,6 +791,7 @@ __global__ void __launch_bounds__(512, 1) gemm_i8_kernel(const ModeJobs J, int64
     begin_item();
     load4(bcur, bA);
     for (;;) {
+      __builtin_amdgcn_s_setprio(1);
       int k = 0;
       for (; k + 64 < kend; k += 128) {
         kstep(k, bA, bB);
