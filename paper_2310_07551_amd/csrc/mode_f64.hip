@@ -355,6 +355,7 @@ __device__ __forceinline__ void modeB_tile(const ModeJob& jb, int64_t lt) {
 
   const int64_t slab = na * (int64_t)n * b;
   constexpr bool fast = MODE == 2;   // every tile interior, n % 32 == 0 (checked at launch)
+  __builtin_amdgcn_s_setprio(1);   // products ahead of another wave's epilogue on the SIMD
   for (int term = 0; term < nterms; ++term) {
     const double* __restrict__ xb = (const double*)jb.X[term] + slab + arow + na * g;
     const double* __restrict__ pbp = (const double*)jb.P[term] + i0 + TN * l + (int64_t)ldp * g;
@@ -463,6 +464,7 @@ __device__ __forceinline__ void modeB_tile(const ModeJob& jb, int64_t lt) {
     }
   }
 
+  __builtin_amdgcn_s_setprio(0);
   // Epilogue (accumulator layout as in the mode-1 kernel): lane (g, l) owns,
   // for each r, the TM consecutive a = a0 + TM g + 4 TM r + (0..TM-1) of
   // column i = i0 + TN l + u.
@@ -552,6 +554,7 @@ __global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int
     // the next pair's first block is loaded during this pair's last one
     const bool next = rep + 1 < reps && pair_of(rep + 1) < npairs;
     const double* xn = next ? xbase(pair_of(rep + 1)) : xb;
+    __builtin_amdgcn_s_setprio(1);   // products ahead of another wave's epilogue on the SIMD
     const int64_t at = q % jb.tiles_a, b = q / jb.tiles_a;
     const int64_t a0 = at * 64;
     const int64_t slab = na * (int64_t)n * b;
@@ -579,6 +582,7 @@ __global__ void __launch_bounds__(512, 1) modeB_lds_kernel(const ModeJobs J, int
         mmablk(p0 + 4 * KB, xq);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     // epilogue as in modeB_tile (TM = TN = 4, every row and column in range)
     double* __restrict__ Y = (double*)jb.Y;
     const double* __restrict__ base = (const double*)jb.base;
