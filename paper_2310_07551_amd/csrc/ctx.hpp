@@ -74,6 +74,9 @@ struct TuckerOut {
   const double* base;
   int nterms;
   TuckerTerm term[kMaxTerms];
+  // SETD_PREC_I8X4 in the order 3, 1, 2 (i8_order312): the terms' X are
+  // already digit buffers along the last mode (launch_stage_slice_i8)
+  bool x_sliced = false;
 };
 
 // Runs all outputs of a group: d grouped launches (or more if a launch would
@@ -88,6 +91,16 @@ int run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int pre
                      void* i8ws = nullptr, size_t i8bytes = 0);
 // Bytes of one int8 digit buffer for any mode of the grid.
 size_t i8_slot_bytes(int d, const int* dims);
+// Whether run_tucker_group takes a d = 3 group of nchains chains in the
+// order 3, 1, 2 (SETD_PREC_I8X4, n1 and n2 in {128, 256}, n3 <= 256, room
+// for 2 nchains + 2 digit buffers).  The first 2 nchains buffers of the
+// workspace then hold the digits emitted between the products, and buffers
+// 2 nchains and 2 nchains + 1 may hold presliced inputs
+// (TuckerOut::x_sliced).
+bool i8_order312(int d, const int* dims, int nchains, size_t i8bytes);
+// Whether the int8 form's products emit the next operand's digits
+// (environment variable SETD_I8_EMIT not 0).
+bool i8_emit();
 // Packs a matrix for the mode kernels of the given arithmetic and direction.
 int pack_for(int prec, const double* M, int n, double scale, int mu, void* out, hipStream_t s);
 // G = g(U) (FP64) and F = K U + G in the Tucker arithmetic's storage type,

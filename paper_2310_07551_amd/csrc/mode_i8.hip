@@ -46,6 +46,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "pointwise.hpp"
 
 namespace setd {
 namespace {
@@ -176,6 +177,74 @@ __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
 // assembled in LDS and leave as whole fibre rows (1 KB per fibre and chunk),
 // so every store of a wave covers contiguous memory.  For n <= 256 each value
 // is read once: it stays in registers between the maximum and the digits.
+// The part of slicing after a thread's values are in registers: the fibre
+// exponents (the largest magnitude key over the 8 threads of a fibre, in
+// red and colexp) and, per 256-long chunk, the digit planes assembled in LDS
+// and written in tile order.  v holds this thread's 32 values of chunk 0;
+// for n > 256 reload(kc) refills it.  mk: this thread's largest key over all
+// chunks.  Ends with a barrier, so the shared arrays may be reused at once.
+template <typename Reload>
+__device__ __forceinline__ void slice_emit(double (&v)[32], int mk, int n, int ldp, int nv, int64_t fib0, int pc,
+                                           int ps, uint8_t* stage, int (*red)[kSliceCols], int* colexp,
+                                           uint8_t* __restrict__ D, int* __restrict__ Dexp, Reload reload) {
+  const int tid = threadIdx.x;
+  red[ps][pc] = mk;
+  __syncthreads();
+  if (tid < kSliceCols) {
+    int mm = red[0][tid];
+    for (int q = 1; q < 8; ++q) mm = max(mm, red[q][tid]);
+    const int e = fibre_exp(mm);
+    colexp[tid] = e;
+    if (tid < nv) Dexp[fib0 + tid] = e;
+  }
+  __syncthreads();
+  const int E = colexp[pc];
+  const bool finite = E != kBadExp;
+  for (int kc = 0; kc < ldp; kc += kSliceChunk) {
+    if (n > kSliceChunk) reload(kc);   // otherwise v still holds the only chunk
+    const int kw = ldp - kc < kSliceChunk ? ldp - kc : kSliceChunk;   // multiple of 64
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int run = 2 * ps + h;
+      if (16 * run >= kw) break;
+      uint32_t d[4][4];   // [group of 4 values][plane]
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t x = digit_word(v[16 * h + 4 * q + e], E);   // unconditional: no branch
+          w[e] = finite ? x : 0u;
+        }
+        digit_planes(w[0], w[1], w[2], w[3], d[q]);
+      }
+      uint8_t* o = stage + pc * kStageRow + 64 * run;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+        *(v4i*)(o + 16 * sp) = v4i{(int)d[0][sp], (int)d[1][sp], (int)d[2][sp], (int)d[3][sp]};
+    }
+    __syncthreads();
+    // 16-byte units in tile order: (local block of 16 fibres, k-step, plane,
+    // slot); unit e = tid + 256 it has slot tid % 64, plane tid / 64 and
+    // (block, k-step) = (it / ksc, it % ksc), the latter kept incrementally
+    const int nks = ldp / 64, ksc = kw / 64;
+    const int ln = tid & 63, sp = tid >> 6;
+    for (int it = 0, cbl = 0, ks = 0; it < kSliceCols * kw / 1024; ++it) {
+      const int pcw = 16 * cbl + (ln >> 2), gg = ln & 3;
+      if (pcw < nv) {
+        const int64_t f = fib0 + pcw;
+        uint8_t* dst = D + (((f >> 4) * nks + kc / 64 + ks) * 4 + sp) * (int64_t)kPlaneBytes + 16 * (4 * (f & 15) + gg);
+        *(v4i*)dst = *(const v4i*)(stage + pcw * kStageRow + 64 * (4 * ks + gg) + 16 * sp);
+      }
+      if (++ks == ksc) {
+        ks = 0;
+        ++cbl;
+      }
+    }
+    __syncthreads();   // the stage is rewritten by the next chunk
+  }
+}
+
 template <bool MODE1>
 __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t per_xcd) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kSliceCols * kStageRow];
@@ -239,61 +308,65 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
 #pragma unroll
     for (int j = 0; j < 32; ++j) mk = max(mk, mag_key(v[j]));
   }
-  red[ps][pc] = mk;
-  __syncthreads();
-  if (tid < kSliceCols) {
-    int mm = red[0][tid];
-    for (int q = 1; q < 8; ++q) mm = max(mm, red[q][tid]);
-    const int e = fibre_exp(mm);
-    colexp[tid] = e;
-    if (tid < nv) Dexp[fib0 + tid] = e;
-  }
-  __syncthreads();
-  const int E = colexp[pc];
-  const bool finite = E != kBadExp;
-  for (int kc = 0; kc < ldp; kc += kSliceChunk) {
-    if (n > kSliceChunk) load(kc);   // otherwise v still holds the only chunk
-    const int kw = ldp - kc < kSliceChunk ? ldp - kc : kSliceChunk;   // multiple of 64
+  slice_emit(v, mk, n, ldp, nv, fib0, pc, ps, stage, red, colexp, D, Dexp, load);
+}
+
+// ---- stage difference and its digits in one pass ----
+// D_c = g_c(U_s) - G_c for both components (the stage difference of
+// Algorithm 2, formed as the stage kernel forms it), cut straight into the
+// digits of its fibres along the last of d modes: fibre a holds the n values
+// a + na p (na = N / n), the layout the slicing kernel writes for modes >= 2
+// with one slab, into D[c].  The FP64 difference never reaches memory.
+// n <= 256.  32 fibres per 256-thread workgroup as in the slicing kernel.
+template <int KIND>
+__global__ void __launch_bounds__(256) stage_slice_i8_kernel(const double* __restrict__ Us,
+                                                             const double* __restrict__ G, int ncomp, int64_t N,
+                                                             int64_t na, int n, int ldp, GParams gp, uint8_t* D0,
+                                                             uint8_t* D1, int64_t per_xcd) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[kSliceCols * kStageRow];
+  __shared__ int red[8][kSliceCols];
+  __shared__ int colexp[kSliceCols];
+  const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
+  if (t * kSliceCols >= na) return;   // uniform over the block
+  const int tid = threadIdx.x, pc = tid & 31, ps = tid >> 5;
+  const int64_t fa0 = t * kSliceCols;
+  const int nv = (int)(na - fa0 < kSliceCols ? na - fa0 : kSliceCols);
+  const bool ok = pc < nv;
+  const int64_t fa = fa0 + (ok ? pc : 0);
+  const int64_t coff = ncomp > 1 ? N : 0;   // the second component (a harmless re-read with one)
+  const int k0 = 32 * ps;
+  double v0[32], v1[32];
+  int m0 = 0, m1 = 0;
+  // eight values at a time: their 32 loads unconditional (clamped to a valid
+  // point) and in flight together, then the differences
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int run = 2 * ps + h;
-      if (16 * run >= kw) break;
-      uint32_t d[4][4];   // [group of 4 values][plane]
+  for (int j0 = 0; j0 < 32; j0 += 8) {
+    double uu[8], ww[8], ga[8], gb[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t w[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t x = digit_word(v[16 * h + 4 * q + e], E);   // unconditional: no branch
-          w[e] = finite ? x : 0u;
-        }
-        digit_planes(w[0], w[1], w[2], w[3], d[q]);
-      }
-      uint8_t* o = stage + pc * kStageRow + 64 * run;
-#pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-        *(v4i*)(o + 16 * sp) = v4i{(int)d[0][sp], (int)d[1][sp], (int)d[2][sp], (int)d[3][sp]};
+    for (int j = 0; j < 8; ++j) {
+      const bool in = ok && k0 + j0 + j < n;
+      const int64_t idx = fa + na * (in ? k0 + j0 + j : 0);
+      uu[j] = Us[idx];
+      ww[j] = Us[coff + idx];
+      ga[j] = G[idx];
+      gb[j] = G[coff + idx];
     }
-    __syncthreads();
-    // 16-byte units in tile order: (local block of 16 fibres, k-step, plane,
-    // slot); unit e = tid + 256 it has slot tid % 64, plane tid / 64 and
-    // (block, k-step) = (it / ksc, it % ksc), the latter kept incrementally
-    const int nks = ldp / 64, ksc = kw / 64;
-    const int ln = tid & 63, sp = tid >> 6;
-    for (int it = 0, cbl = 0, ks = 0; it < kSliceCols * kw / 1024; ++it) {
-      const int pcw = 16 * cbl + (ln >> 2), gg = ln & 3;
-      if (pcw < nv) {
-        const int64_t f = fib0 + pcw;
-        uint8_t* dst = D + (((f >> 4) * nks + kc / 64 + ks) * 4 + sp) * (int64_t)kPlaneBytes + 16 * (4 * (f & 15) + gg);
-        *(v4i*)dst = *(const v4i*)(stage + pcw * kStageRow + 64 * (4 * ks + gg) + 16 * sp);
-      }
-      if (++ks == ksc) {
-        ks = 0;
-        ++cbl;
-      }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool in = ok && k0 + j0 + j < n;
+      double g0, g1;
+      reaction_of<KIND>(gp, uu[j], ncomp > 1 ? ww[j] : 0.0, g0, g1);
+      v0[j0 + j] = in ? g0 - ga[j] : 0.0;
+      v1[j0 + j] = in && ncomp > 1 ? g1 - gb[j] : 0.0;
+      m0 = max(m0, mag_key(v0[j0 + j]));
+      m1 = max(m1, mag_key(v1[j0 + j]));
     }
-    __syncthreads();   // the stage is rewritten by the next chunk
   }
+  const int64_t ntot16 = (na + 15) & ~(int64_t)15;
+  auto none = [](int) {};
+  slice_emit(v0, m0, n, ldp, nv, fa0, pc, ps, stage, red, colexp, D0, (int*)(D0 + ntot16 * 4 * (int64_t)ldp), none);
+  if (ncomp > 1)
+    slice_emit(v1, m1, n, ldp, nv, fa0, pc, ps, stage, red, colexp, D1, (int*)(D1 + ntot16 * 4 * (int64_t)ldp), none);
 }
 
 // ---- digit GEMM ----
@@ -827,6 +900,23 @@ size_t packed_bytes_i8(int n) {
 size_t i8_digit_bytes(int64_t N, int n) {
   const int64_t fibres = N / n;
   return (size_t)round_up(round_up(fibres, (int64_t)16) * 4 * packed_ld(n) + 4 * fibres, 256);
+}
+
+int launch_stage_slice_i8(const double* Us, const double* G, int ncomp, int64_t N, int n, const GParams& gp,
+                          void* const* D, hipStream_t s) {
+  if (n < 1 || n > kSliceChunk || N % n != 0 || ncomp < 1 || ncomp > 2) {
+    set_error("stage slicing needs n in 1..%d dividing N and one or two components", kSliceChunk);
+    return SETD_EINVAL;
+  }
+  const int64_t na = N / n;
+  const int64_t per = ceil_div(ceil_div(na, kSliceCols), 8);
+  ProfScope prof(s, kProfModeBLP, 0.0, (double)ncomp * N * (16.0 + 4.0));
+  auto kern = gp.kind == SETD_G_FHN ? stage_slice_i8_kernel<SETD_G_FHN>
+             : gp.kind == SETD_G_SCHNAKENBERG ? stage_slice_i8_kernel<SETD_G_SCHNAKENBERG> : stage_slice_i8_kernel<0>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(per * 8)), dim3(256), 0, s, Us, G, ncomp, N, na, n, packed_ld(n), gp,
+                     (uint8_t*)D[0], (uint8_t*)(ncomp > 1 ? D[1] : D[0]), per);
+  SETD_LAUNCHED();
+  return SETD_OK;
 }
 
 int pack_matrix_i8(const double* M, int n, double scale, void* out, hipStream_t s) {

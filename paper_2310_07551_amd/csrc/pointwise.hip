@@ -140,20 +140,6 @@ int launch_copy_convert(const double* x, void* y, int64_t n, DType out, hipStrea
 // ---------------------------------------------------------------------------
 // reaction, G/F and stage kernels
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void reaction(const GParams& P, double u, double v, double& g1, double& g2) {
-  if (P.kind == SETD_G_SCHNAKENBERG) {
-    const double u2v = u * u * v;
-    g1 = P.p[0] * (P.p[1] - u + u2v);
-    g2 = P.p[0] * (P.p[2] - u2v);
-  } else if (P.kind == SETD_G_FHN) {
-    const double rho = P.p[3];
-    g1 = rho * (u - u * u * u - v);
-    g2 = rho * P.p[0] * (u - P.p[1] * v - P.p[2]);
-  } else {
-    g1 = 0.0;
-    g2 = 0.0;
-  }
-}
 
 // Per-point bodies.  u holds ncomp fields, component c at u + c * cs;
 // point idx has grid indices (i1, i2, i3) with i1 fastest.

@@ -13,6 +13,32 @@ struct GParams {
   double p[4];
 };
 
+// g(u, v) of the two-component kinetics (eq. twocompdisc), rho included:
+// KIND is SETD_G_SCHNAKENBERG, SETD_G_FHN or anything else for g = 0.
+template <int KIND>
+__device__ __forceinline__ void reaction_of(const GParams& P, double u, double v, double& g1, double& g2) {
+  if constexpr (KIND == SETD_G_SCHNAKENBERG) {
+    const double u2v = u * u * v;
+    g1 = P.p[0] * (P.p[1] - u + u2v);
+    g2 = P.p[0] * (P.p[2] - u2v);
+  } else if constexpr (KIND == SETD_G_FHN) {
+    const double rho = P.p[3];
+    g1 = rho * (u - u * u * u - v);
+    g2 = rho * P.p[0] * (u - P.p[1] * v - P.p[2]);
+  } else {
+    g1 = 0.0;
+    g2 = 0.0;
+  }
+}
+__device__ __forceinline__ void reaction(const GParams& P, double u, double v, double& g1, double& g2) {
+  if (P.kind == SETD_G_SCHNAKENBERG)
+    reaction_of<SETD_G_SCHNAKENBERG>(P, u, v, g1, g2);
+  else if (P.kind == SETD_G_FHN)
+    reaction_of<SETD_G_FHN>(P, u, v, g1, g2);
+  else
+    reaction_of<0>(P, u, v, g1, g2);
+}
+
 // Tridiagonal coefficients of A_mu^(c): index c*3 + mu; arrays of n_mu
 // (device).  lo[i] = A[i, i-1], di[i] = A[i, i], up[i] = A[i, i+1].
 struct StencilSet {
@@ -42,6 +68,12 @@ int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* d
 int launch_g(const double* u, int ncomp, int64_t N, const GParams& gp, double* G, hipStream_t s);
 int launch_stage_d(const double* Us, const double* G, int ncomp, int64_t N, const GParams& gp, void* D,
                    DType dtype, hipStream_t s);
+// SETD_PREC_I8X4 (mode_i8.hip): D_c = g_c(Us) - G_c for the ncomp (1 or 2)
+// components, written only as the int8 digits of its fibres along the last
+// mode of size n (n <= 256, dividing N) into the digit buffers D[c]; the
+// bits are those the slicing kernel cuts from the FP64 D of launch_stage_d.
+int launch_stage_slice_i8(const double* Us, const double* G, int ncomp, int64_t N, int n, const GParams& gp,
+                          void* const* D, hipStream_t s);
 size_t norm_workspace_bytes();
 int launch_norms(const double* x, const double* y, int64_t n, double* ws, hipStream_t s);
 

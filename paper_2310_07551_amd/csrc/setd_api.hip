@@ -174,6 +174,23 @@ size_t setd::i8_slot_bytes(int d, const int* dims) {
   return b;
 }
 
+namespace {
+bool i8_emit_on() {
+  // SETD_I8_EMIT=0 makes every product write its FP64 result and the next one
+  // slice it (same order of the modes): the emitted digits must equal these
+  const char* e = std::getenv("SETD_I8_EMIT");
+  return e == nullptr || e[0] != '0';
+}
+bool fusable_side(int m) { return m == 128 || m == 256; }
+}  // namespace
+
+bool setd::i8_order312(int d, const int* dims, int nchains, size_t i8bytes) {
+  return d == 3 && fusable_side(dims[0]) && fusable_side(dims[1]) && dims[2] <= 256 &&
+         (size_t)(2 * nchains + 2) * i8_slot_bytes(d, dims) <= i8bytes;
+}
+
+bool setd::i8_emit() { return i8_emit_on(); }
+
 int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, int prec, hipStream_t s,
                            void* i8ws, size_t i8bytes) {
   int64_t N = 1;
@@ -182,23 +199,28 @@ int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, i
   int nchains = 0;
   for (int o = 0; o < nouts; ++o) nchains += outs[o].nterms;
   const size_t slot = prec == SETD_PREC_I8X4 ? i8_slot_bytes(d, dims) : 0;
-  auto fusable = [](int m) { return m == 128 || m == 256; };
-  // SETD_I8_EMIT=0 makes every product write its FP64 result and the next one
-  // slice it (same order of the modes): the emitted digits must equal these
-  const char* emit_env = std::getenv("SETD_I8_EMIT");
-  const bool emit = emit_env == nullptr || emit_env[0] != '0';
+  const bool emit = i8_emit_on();
+  bool sliced_in = false;
+  for (int o = 0; o < nouts; ++o) sliced_in = sliced_in || outs[o].x_sliced;
   // I8X4, d = 3, n1 and n2 in {128, 256}, n3 <= 256: the products run in the
   // order 3, 1, 2 (the modes commute), so that both intermediates are emitted
   // as digits by the product before them: mode 3 writes the mode-1 digits
   // (slot A of the chain), mode 1 the mode-2 digits (slot B), and only the
-  // inputs are sliced (into the slots after them)
-  if (prec == SETD_PREC_I8X4 && d == 3 && fusable(dims[0]) && fusable(dims[1]) && dims[2] <= 256 &&
-      (size_t)(2 * nchains + 1) * slot <= i8bytes) {
+  // inputs are sliced (into the slots after them), unless they come sliced
+  if (prec == SETD_PREC_I8X4 && i8_order312(d, dims, nchains, i8bytes)) {
     char* base_ws = (char*)i8ws;
     auto slotA = [&](int c) { return (void*)(base_ws + (size_t)c * slot); };
     auto slotB = [&](int c) { return (void*)(base_ws + (size_t)(nchains + c) * slot); };
     LaunchKind k3{false, prec, DType::F64, base_ws + (size_t)2 * nchains * slot, i8bytes - (size_t)2 * nchains * slot};
     k3.fuse_next = emit ? dims[0] : 0;
+    if (sliced_in) {
+      for (int o = 0; o < nouts; ++o)
+        if (!outs[o].x_sliced) {
+          set_error("a Tucker group mixes sliced and FP64 inputs");
+          return SETD_EINVAL;
+        }
+      k3.presliced = true;
+    }
     LaunchKind k1{true, prec, DType::F64, i8ws, i8bytes};
     k1.presliced = emit;
     k1.fuse_next = emit ? dims[1] : 0;
@@ -244,6 +266,10 @@ int setd::run_tucker_group(int d, const int* dims, TuckerOut* outs, int nouts, i
   // I8X4 with n1 <= 256 and n2 in {128, 256}: the mode-1 products emit the
   // mode-2 digits straight into one buffer per chain (the first slots of the
   // workspace; the slicing passes get the rest), and mode 2 reads them
+  if (sliced_in) {
+    set_error("sliced Tucker inputs need the int8 form in the order 3, 1, 2");
+    return SETD_EINVAL;
+  }
   const bool fuse = emit && prec == SETD_PREC_I8X4 && d >= 2 && dims[0] <= 256 && (dims[1] == 128 || dims[1] == 256) &&
                     (size_t)(nchains + 1) * slot <= i8bytes;
   char* chain_digits = (char*)i8ws;
@@ -497,9 +523,25 @@ int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, co
     }
     SETD_TRY(run_tucker_group(d, c->dims, outs, no, prec, s, c->i8_mem.p, c->i8_mem.bytes));
   }
-  // 3. D2 = g(U2) - G
-  SETD_TRY(launch_stage_d(b.U2, b.G, nc, N, gp, b.D2, tdt, s));
-  // 4. U3 += 4tau/3 S_2(2tau/3) D2
+  // D = g(U_s) - G, the input of the next group.  The int8 form in the order
+  // 3, 1, 2 writes only D's digits along mode 3 (the stage difference and
+  // the slicing in one pass), unless the stage quantities are being recorded.
+  auto stage_diff = [&](const double* Us, void* Dbuf, TuckerOut* outs) -> int {
+    const bool own = b.D2 == (void*)c->D && b.D3 == (void*)c->D;
+    if (prec == SETD_PREC_I8X4 && own && i8_emit() && i8_order312(d, c->dims, nc * T, c->i8_mem.bytes)) {
+      const size_t slot = i8_slot_bytes(d, c->dims);
+      void* dg[2];
+      for (int cc = 0; cc < 2; ++cc) dg[cc] = (char*)c->i8_mem.p + (size_t)(2 * nc * T + cc) * slot;
+      SETD_TRY(launch_stage_slice_i8(Us, b.G, nc, N, c->dims[2], gp, dg, s));
+      for (int cc = 0; cc < nc; ++cc) {
+        outs[cc].x_sliced = true;
+        for (int t = 0; t < T; ++t) outs[cc].term[t].X = dg[cc];
+      }
+      return SETD_OK;
+    }
+    return launch_stage_d(Us, b.G, nc, N, gp, Dbuf, tdt, s);
+  };
+  // 3., 4. D2 = g(U2) - G; U3 += 4tau/3 S_2(2tau/3) D2
   {
     TuckerOut outs[2];
     for (int cc = 0; cc < nc; ++cc) {
@@ -510,11 +552,10 @@ int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, co
       for (int t = 0; t < T; ++t)
         o.term[t] = {D2c_(cc), c->bank[cc][e32][t], 4.0 * tau / 3.0 * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
+    SETD_TRY(stage_diff(b.U2, b.D2, outs));
     SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s, c->i8_mem.p, c->i8_mem.bytes));
   }
-  // 5. D3 = g(U3) - G
-  SETD_TRY(launch_stage_d(b.U3, b.G, nc, N, gp, b.D3, tdt, s));
-  // 6. U = W + 3tau/2 S_2(tau) D
+  // 5., 6. D3 = g(U3) - G; U = W + 3tau/2 S_2(tau) D3
   {
     TuckerOut outs[2];
     for (int cc = 0; cc < nc; ++cc) {
@@ -525,6 +566,7 @@ int setd::step_with(setd_ctx* c, double* u, const GParams& gp, hipStream_t s, co
       for (int t = 0; t < T; ++t)
         o.term[t] = {D3c_(cc), c->bank[cc][ef2][t], 1.5 * tau * S2.eta[t], c->Y1[cc][t], c->Y2[cc][t]};
     }
+    SETD_TRY(stage_diff(b.U3, b.D3, outs));
     SETD_TRY(run_tucker_group(d, c->dims, outs, nc, prec, s, c->i8_mem.p, c->i8_mem.bytes));
   }
   return SETD_OK;

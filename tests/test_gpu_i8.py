@@ -255,3 +255,24 @@ def test_emitted_digits_equal_sliced_digits_i8(dims, monkeypatch):
         out.append(host(Wd, prob.dims))
     say("emitted == sliced", dims)
     assert np.array_equal(out[0], out[1]), (dims, np.abs(out[0] - out[1]).max())
+
+
+@pytest.mark.parametrize("dims", [(128, 128, 40), (256, 128, 100), (128, 256, 256)])
+def test_fused_stage_slicing_bit_identical_i8(dims, monkeypatch):
+    """In the order 3, 1, 2 the stage differences D2 = g(U2) - G and
+    D3 = g(U3) - G are cut into their mode-3 digits in the pass that forms
+    them, without an FP64 D.  Whole steps agree to the last bit with the
+    steps that form D in FP64 and slice it afterwards (SETD_I8_EMIT=0, which
+    also turns the digit emission between products off; same order of the
+    modes), and stay within the reduced-precision bar of the oracle."""
+    prob = wl.fhn_3d(dims=dims)
+    runs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("SETD_I8_EMIT", flag)
+        runs.append(_run(prob, 3))
+    say("fused stage slicing", dims)
+    for c in range(2):
+        assert np.array_equal(runs[0][c], runs[1][c]), (dims, c, np.abs(runs[0][c] - runs[1][c]).max())
+    ref = oracle.integrate(prob.U0, prob.A, prob.tau, 3, prob.g_kind, prob.params)
+    for c in range(2):
+        assert rel_l2(runs[0][c], ref[c]) < TOL, (dims, c)
