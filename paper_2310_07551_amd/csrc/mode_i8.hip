@@ -177,22 +177,28 @@ __device__ __forceinline__ int64_t remap_xcd_i8(int64_t bid, int64_t per_xcd) {
 // assembled in LDS and leave as whole fibre rows (1 KB per fibre and chunk),
 // so every store of a wave covers contiguous memory.  For n <= 256 each value
 // is read once: it stays in registers between the maximum and the digits.
-// The part of slicing after a thread's values are in registers: the fibre
-// exponents (the largest magnitude key over the 8 threads of a fibre, in
-// red and colexp) and, per 256-long chunk, the digit planes assembled in LDS
-// and written in tile order.  v holds this thread's 32 values of chunk 0;
-// for n > 256 reload(kc) refills it.  mk: this thread's largest key over all
-// chunks.  Ends with a barrier, so the shared arrays may be reused at once.
-template <typename Reload>
-__device__ __forceinline__ void slice_emit(double (&v)[32], int mk, int n, int ldp, int nv, int64_t fib0, int pc,
-                                           int ps, uint8_t* stage, int (*red)[kSliceCols], int* colexp,
-                                           uint8_t* __restrict__ D, int* __restrict__ Dexp, Reload reload) {
+// The part of slicing after a thread's values are in registers, for a
+// 256-thread workgroup of COLS fibres x 256 / COLS threads of COLS
+// consecutive values each (COLS 32: 8 threads x 32 values; COLS 16: 16
+// threads x 16 values): the fibre exponents (the largest
+// magnitude key over the threads of a fibre, in red and colexp) and, per
+// 256-long chunk, the digit planes assembled in LDS and written in tile
+// order.  v holds this thread's values of chunk 0; for n > 256 reload(kc)
+// refills it.  mk: this thread's largest key over all chunks.  Ends with a
+// barrier, so the shared arrays may be reused at once.
+template <int COLS, typename Reload>
+__device__ __forceinline__ void slice_emit(double (&v)[kSliceChunk * COLS / 256], int mk, int n, int ldp, int nv,
+                                           int64_t fib0, int pc, int ps, uint8_t* stage, int (*red)[COLS],
+                                           int* colexp, uint8_t* __restrict__ D, int* __restrict__ Dexp,
+                                           Reload reload) {
+  constexpr int TPF = 256 / COLS;                 // threads per fibre
+  constexpr int RUNS = kSliceChunk / (16 * TPF);  // 16-value runs per thread and chunk
   const int tid = threadIdx.x;
   red[ps][pc] = mk;
   __syncthreads();
-  if (tid < kSliceCols) {
+  if (tid < COLS) {
     int mm = red[0][tid];
-    for (int q = 1; q < 8; ++q) mm = max(mm, red[q][tid]);
+    for (int q = 1; q < TPF; ++q) mm = max(mm, red[q][tid]);
     const int e = fibre_exp(mm);
     colexp[tid] = e;
     if (tid < nv) Dexp[fib0 + tid] = e;
@@ -204,8 +210,8 @@ __device__ __forceinline__ void slice_emit(double (&v)[32], int mk, int n, int l
     if (n > kSliceChunk) reload(kc);   // otherwise v still holds the only chunk
     const int kw = ldp - kc < kSliceChunk ? ldp - kc : kSliceChunk;   // multiple of 64
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int run = 2 * ps + h;
+    for (int h = 0; h < RUNS; ++h) {
+      const int run = RUNS * ps + h;
       if (16 * run >= kw) break;
       uint32_t d[4][4];   // [group of 4 values][plane]
 #pragma unroll
@@ -229,7 +235,7 @@ __device__ __forceinline__ void slice_emit(double (&v)[32], int mk, int n, int l
     // (block, k-step) = (it / ksc, it % ksc), the latter kept incrementally
     const int nks = ldp / 64, ksc = kw / 64;
     const int ln = tid & 63, sp = tid >> 6;
-    for (int it = 0, cbl = 0, ks = 0; it < kSliceCols * kw / 1024; ++it) {
+    for (int it = 0, cbl = 0, ks = 0; it < COLS * kw / 1024; ++it) {
       const int pcw = 16 * cbl + (ln >> 2), gg = ln & 3;
       if (pcw < nv) {
         const int64_t f = fib0 + pcw;
@@ -308,7 +314,7 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
 #pragma unroll
     for (int j = 0; j < 32; ++j) mk = max(mk, mag_key(v[j]));
   }
-  slice_emit(v, mk, n, ldp, nv, fib0, pc, ps, stage, red, colexp, D, Dexp, load);
+  slice_emit<kSliceCols>(v, mk, n, ldp, nv, fib0, pc, ps, stage, red, colexp, D, Dexp, load);
 }
 
 // ---- stage difference and its digits in one pass ----
@@ -323,50 +329,49 @@ __global__ void __launch_bounds__(256) stage_slice_i8_kernel(const double* __res
                                                              const double* __restrict__ G, int ncomp, int64_t N,
                                                              int64_t na, int n, int ldp, GParams gp, uint8_t* D0,
                                                              uint8_t* D1, int64_t per_xcd) {
-  __shared__ __attribute__((aligned(16))) uint8_t stage[kSliceCols * kStageRow];
-  __shared__ int red[8][kSliceCols];
-  __shared__ int colexp[kSliceCols];
+  constexpr int COLS = 16, VPT = 16;   // 16 fibres x 16 threads x 16 values
+  __shared__ __attribute__((aligned(16))) uint8_t stage[COLS * kStageRow];
+  __shared__ int red[256 / COLS][COLS];
+  __shared__ int colexp[COLS];
   const int64_t t = remap_xcd_i8(blockIdx.x, per_xcd);
-  if (t * kSliceCols >= na) return;   // uniform over the block
-  const int tid = threadIdx.x, pc = tid & 31, ps = tid >> 5;
-  const int64_t fa0 = t * kSliceCols;
-  const int nv = (int)(na - fa0 < kSliceCols ? na - fa0 : kSliceCols);
+  if (t * COLS >= na) return;   // uniform over the block
+  const int tid = threadIdx.x, pc = tid & (COLS - 1), ps = tid / COLS;
+  const int64_t fa0 = t * COLS;
+  const int nv = (int)(na - fa0 < COLS ? na - fa0 : COLS);
   const bool ok = pc < nv;
   const int64_t fa = fa0 + (ok ? pc : 0);
   const int64_t coff = ncomp > 1 ? N : 0;   // the second component (a harmless re-read with one)
-  const int k0 = 32 * ps;
-  double v0[32], v1[32];
+  const int k0 = VPT * ps;
+  double v0[VPT], v1[VPT];
   int m0 = 0, m1 = 0;
-  // eight values at a time: their 32 loads unconditional (clamped to a valid
-  // point) and in flight together, then the differences
+  // the 64 loads unconditional (clamped to a valid point) and in flight together
+  double uu[VPT], ww[VPT], ga[VPT], gb[VPT];
 #pragma unroll
-  for (int j0 = 0; j0 < 32; j0 += 8) {
-    double uu[8], ww[8], ga[8], gb[8];
+  for (int j = 0; j < VPT; ++j) {
+    const bool in = ok && k0 + j < n;
+    const int64_t idx = fa + na * (in ? k0 + j : 0);
+    uu[j] = Us[idx];
+    ww[j] = Us[coff + idx];
+    ga[j] = G[idx];
+    gb[j] = G[coff + idx];
+  }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const bool in = ok && k0 + j0 + j < n;
-      const int64_t idx = fa + na * (in ? k0 + j0 + j : 0);
-      uu[j] = Us[idx];
-      ww[j] = Us[coff + idx];
-      ga[j] = G[idx];
-      gb[j] = G[coff + idx];
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const bool in = ok && k0 + j0 + j < n;
-      double g0, g1;
-      reaction_of<KIND>(gp, uu[j], ncomp > 1 ? ww[j] : 0.0, g0, g1);
-      v0[j0 + j] = in ? g0 - ga[j] : 0.0;
-      v1[j0 + j] = in && ncomp > 1 ? g1 - gb[j] : 0.0;
-      m0 = max(m0, mag_key(v0[j0 + j]));
-      m1 = max(m1, mag_key(v1[j0 + j]));
-    }
+  for (int j = 0; j < VPT; ++j) {
+    const bool in = ok && k0 + j < n;
+    double g0, g1;
+    reaction_of<KIND>(gp, uu[j], ncomp > 1 ? ww[j] : 0.0, g0, g1);
+    v0[j] = in ? g0 - ga[j] : 0.0;
+    v1[j] = in && ncomp > 1 ? g1 - gb[j] : 0.0;
+    m0 = max(m0, mag_key(v0[j]));
+    m1 = max(m1, mag_key(v1[j]));
   }
   const int64_t ntot16 = (na + 15) & ~(int64_t)15;
   auto none = [](int) {};
-  slice_emit(v0, m0, n, ldp, nv, fa0, pc, ps, stage, red, colexp, D0, (int*)(D0 + ntot16 * 4 * (int64_t)ldp), none);
+  slice_emit<COLS>(v0, m0, n, ldp, nv, fa0, pc, ps, stage, red, colexp, D0, (int*)(D0 + ntot16 * 4 * (int64_t)ldp),
+                   none);
   if (ncomp > 1)
-    slice_emit(v1, m1, n, ldp, nv, fa0, pc, ps, stage, red, colexp, D1, (int*)(D1 + ntot16 * 4 * (int64_t)ldp), none);
+    slice_emit<COLS>(v1, m1, n, ldp, nv, fa0, pc, ps, stage, red, colexp, D1,
+                     (int*)(D1 + ntot16 * 4 * (int64_t)ldp), none);
 }
 
 // ---- digit GEMM ----
@@ -909,7 +914,7 @@ int launch_stage_slice_i8(const double* Us, const double* G, int ncomp, int64_t 
     return SETD_EINVAL;
   }
   const int64_t na = N / n;
-  const int64_t per = ceil_div(ceil_div(na, kSliceCols), 8);
+  const int64_t per = ceil_div(ceil_div(na, 16), 8);   // 16 fibres per workgroup
   ProfScope prof(s, kProfModeBLP, 0.0, (double)ncomp * N * (16.0 + 4.0));
   auto kern = gp.kind == SETD_G_FHN ? stage_slice_i8_kernel<SETD_G_FHN>
              : gp.kind == SETD_G_SCHNAKENBERG ? stage_slice_i8_kernel<SETD_G_SCHNAKENBERG> : stage_slice_i8_kernel<0>;
