@@ -915,7 +915,9 @@ int launch_stage_slice_i8(const double* Us, const double* G, int ncomp, int64_t 
   }
   const int64_t na = N / n;
   const int64_t per = ceil_div(ceil_div(na, 16), 8);   // 16 fibres per workgroup
-  ProfScope prof(s, kProfModeBLP, 0.0, (double)ncomp * N * (16.0 + 4.0));
+  // timed with the pointwise kernels: it does the stage kernel's work (and a
+  // slicing pass), no mode product
+  ProfScope prof(s, kProfPointwise, 0.0, (double)ncomp * N * (16.0 + 4.0));
   auto kern = gp.kind == SETD_G_FHN ? stage_slice_i8_kernel<SETD_G_FHN>
              : gp.kind == SETD_G_SCHNAKENBERG ? stage_slice_i8_kernel<SETD_G_SCHNAKENBERG> : stage_slice_i8_kernel<0>;
   hipLaunchKernelGGL(kern, dim3((unsigned)(per * 8)), dim3(256), 0, s, Us, G, ncomp, N, na, n, packed_ld(n), gp,
