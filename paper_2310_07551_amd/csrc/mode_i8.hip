@@ -323,7 +323,9 @@ __global__ void __launch_bounds__(256) slice_i8_kernel(const ModeJobs J, int64_t
 // digits of its fibres along the last of d modes: fibre a holds the n values
 // a + na p (na = N / n), the layout the slicing kernel writes for modes >= 2
 // with one slab, into D[c].  The FP64 difference never reaches memory.
-// n <= 256.  32 fibres per 256-thread workgroup as in the slicing kernel.
+// n <= 256.  A 256-thread workgroup takes 16 fibres, 16 threads per fibre and
+// 16 consecutive values per thread (the slicing kernel's 32 x 8 x 32 shape
+// would hold 4 x 32 operands per thread here).
 template <int KIND>
 __global__ void __launch_bounds__(256) stage_slice_i8_kernel(const double* __restrict__ Us,
                                                              const double* __restrict__ G, int ncomp, int64_t N,
