@@ -206,17 +206,22 @@ __device__ __forceinline__ void stage_d_point(const double* __restrict__ Us, con
 // i2 neighbour is loaded once; the i1 and i3 coefficients are loaded once
 // per thread.  The grid is (ceil(n1 / blockDim.x), ceil(n2 / RB), n3): no
 // integer division per point.  The sums are formed in the order of
-// gf_point_at (direction by direction).
-template <typename TF, int RB>
-__global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64_t N, int d, int n1, int n2,
-                                  int n3, StencilSet S, GParams gp, double* __restrict__ G, TF* __restrict__ F) {
+// gf_point_at (direction by direction).  Every neighbour is loaded without
+// a branch, from a clamped index, and a neighbour past the boundary gets a
+// zero coefficient (an exact +0 term); the component count NC is a template
+// argument, so the component loops unroll.  Behind a branch or a run-time
+// loop each load would be waited for on its own before the next one issues.
+template <typename TF, int RB, int NC>
+__global__ void gf_stencil_kernel(const double* __restrict__ u, int64_t N, int d, int n1, int n2, int n3,
+                                  StencilSet S, GParams gp, double* __restrict__ G, TF* __restrict__ F) {
   const int i1 = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i1 >= n1) return;
   const int r0 = (int)blockIdx.y * RB, i3 = (int)blockIdx.z;
   const int64_t s2 = n1, s3 = (int64_t)n1 * n2;
   const int64_t base = (int64_t)i3 * s3 + i1;
   double d1[2], l1[2], u1[2], d3[2], l3[2], u3[2], prv[2], cur[2];
-  for (int c = 0; c < ncomp; ++c) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
     const int o1 = c * 3, o3 = c * 3 + 2;
     d1[c] = S.di[o1][i1];
     l1[c] = i1 > 0 ? S.lo[o1][i1] : 0.0;
@@ -227,31 +232,40 @@ __global__ void gf_stencil_kernel(const double* __restrict__ u, int ncomp, int64
     prv[c] = r0 > 0 ? u[c * N + base + (int64_t)(r0 - 1) * s2] : 0.0;
     cur[c] = u[c * N + base + (int64_t)r0 * s2];
   }
+  const int64_t m1 = i1 > 0 ? -1 : 0, p1 = i1 + 1 < n1 ? 1 : 0;                  // clamped i1 neighbours
+  const int64_t m3 = (d == 3 && i3 > 0) ? -s3 : 0, p3 = (d == 3 && i3 + 1 < n3) ? s3 : 0;   // and i3
+#pragma unroll
   for (int r = 0; r < RB; ++r) {
     const int i2 = r0 + r;
     if (i2 >= n2) break;
     const int64_t idx = base + (int64_t)i2 * s2;
+    const bool has_next = i2 + 1 < n2;
     double nxt[2] = {0.0, 0.0}, g[2];
-    for (int c = 0; c < ncomp; ++c) nxt[c] = i2 + 1 < n2 ? u[c * N + idx + s2] : 0.0;
-    reaction(gp, cur[0], ncomp > 1 ? cur[1] : 0.0, g[0], g[1]);
-    for (int c = 0; c < ncomp; ++c) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double x = u[c * N + idx + (has_next ? s2 : 0)];
+      nxt[c] = has_next ? x : 0.0;
+    }
+    reaction(gp, cur[0], NC > 1 ? cur[1] : 0.0, g[0], g[1]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
       const double* __restrict__ uu = u + (int64_t)c * N;
       const int o2 = c * 3 + 1;
+      // l1, u1, l3, u3 are zero past the boundary; so are prv and nxt
+      const double lo2 = i2 > 0 ? S.lo[o2][i2] : 0.0, up2 = has_next ? S.up[o2][i2] : 0.0;
       double t = d1[c] * cur[c];
-      if (i1 > 0) t += l1[c] * uu[idx - 1];
-      if (i1 + 1 < n1) t += u1[c] * uu[idx + 1];
+      t += l1[c] * uu[idx + m1];
+      t += u1[c] * uu[idx + p1];
       double k = 0.0;
       k += t;
       t = S.di[o2][i2] * cur[c];
-      if (i2 > 0) t += S.lo[o2][i2] * prv[c];
-      if (i2 + 1 < n2) t += S.up[o2][i2] * nxt[c];
+      t += lo2 * prv[c];
+      t += up2 * nxt[c];
       k += t;
-      if (d == 3) {
-        t = d3[c] * cur[c];
-        if (i3 > 0) t += l3[c] * uu[idx - s3];
-        if (i3 + 1 < n3) t += u3[c] * uu[idx + s3];
-        k += t;
-      }
+      t = d3[c] * cur[c];   // d == 2: zero coefficients, offsets 0 (the point itself)
+      t += l3[c] * uu[idx + m3];
+      t += u3[c] * uu[idx + p3];
+      k += t;
       G[(int64_t)c * N + idx] = g[c];
       F[(int64_t)c * N + idx] = (TF)(k + g[c]);
       prv[c] = cur[c];
@@ -325,12 +339,18 @@ int launch_gf_stencil(const double* u, int ncomp, int64_t N, int d, const int* d
   const dim3 grid((unsigned)ceil_div(dims[0], bx), (unsigned)ceil_div(dims[1], RB), (unsigned)n3);
   // reads u once, writes G (FP64) and F
   ProfScope prof(s, kProfPointwise, 0.0, (double)N * ncomp * (8 + 8 + (ftype == DType::F64 ? 8 : 4)));
-  if (ftype == DType::F64)
-    hipLaunchKernelGGL((gf_stencil_kernel<double, RB>), grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3,
-                       S, gp, G, (double*)F);
-  else
-    hipLaunchKernelGGL((gf_stencil_kernel<float, RB>), grid, dim3(bx), 0, s, u, ncomp, N, d, dims[0], dims[1], n3, S,
-                       gp, G, (float*)F);
+  auto launch = [&](auto tf, auto nc) {
+    using TF = decltype(tf);
+    hipLaunchKernelGGL((gf_stencil_kernel<TF, RB, decltype(nc)::value>), grid, dim3(bx), 0, s, u, N, d, dims[0],
+                       dims[1], n3, S, gp, G, (TF*)F);
+  };
+  if (ftype == DType::F64) {
+    if (ncomp == 1) launch(0.0, std::integral_constant<int, 1>{});
+    else launch(0.0, std::integral_constant<int, 2>{});
+  } else {
+    if (ncomp == 1) launch(0.0f, std::integral_constant<int, 1>{});
+    else launch(0.0f, std::integral_constant<int, 2>{});
+  }
   SETD_LAUNCHED();
   return SETD_OK;
 }
