@@ -141,29 +141,38 @@ int launch_copy_convert(const double* x, void* y, int64_t n, DType out, hipStrea
 // reaction, G/F and stage kernels
 // ---------------------------------------------------------------------------
 
-// Per-point bodies.  u holds ncomp fields, component c at u + c * cs;
-// point idx has grid indices (i1, i2, i3) with i1 fastest.
-template <typename TF>
+// Per-point bodies.  u holds NC fields, component c at u + c * cs;
+// point idx has grid indices (i1, i2, i3) with i1 fastest.  D and NC are
+// template arguments and every load is unconditional (a clamped index and a
+// zero coefficient past the boundary, an exact +0 term), so that a point's
+// loads are in flight together: behind a branch, or in a loop with a
+// run-time trip count, each would be waited for on its own.
+template <typename TF, int D, int NC>
 __device__ __forceinline__ void gf_point_at(const double* __restrict__ u, int64_t cs, int64_t idx, int i1, int i2,
-                                            int i3, int ncomp, int d, int n1, int n2, int n3, const StencilSet& S,
-                                            const GParams& gp, double* __restrict__ G, TF* __restrict__ F) {
+                                            int i3, int n1, int n2, int n3, const StencilSet& S, const GParams& gp,
+                                            double* __restrict__ G, TF* __restrict__ F) {
   const int idxs[3] = {i1, i2, i3};
   const int ns[3] = {n1, n2, n3};
   const int64_t strides[3] = {1, (int64_t)n1, (int64_t)n1 * n2};
 
-  double uc[2], g[2];
-  uc[0] = u[idx];
-  uc[1] = (ncomp > 1) ? u[cs + idx] : 0.0;
+  double uc[2] = {0.0, 0.0}, g[2];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) uc[c] = u[(int64_t)c * cs + idx];
   reaction(gp, uc[0], uc[1], g[0], g[1]);
-  for (int c = 0; c < ncomp; ++c) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
     const double* __restrict__ uu = u + (int64_t)c * cs;
     double k = 0.0;
-    for (int mu = 0; mu < d; ++mu) {
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
       const int i = idxs[mu];
       const int off = c * 3 + mu;
+      const bool has_lo = i > 0, has_up = i + 1 < ns[mu];
+      const double lo = has_lo ? S.lo[off][i] : 0.0, up = has_up ? S.up[off][i] : 0.0;
+      const double xl = uu[idx - (has_lo ? strides[mu] : 0)], xu = uu[idx + (has_up ? strides[mu] : 0)];
       double t = S.di[off][i] * uc[c];
-      if (i > 0) t += S.lo[off][i] * uu[idx - strides[mu]];
-      if (i + 1 < ns[mu]) t += S.up[off][i] * uu[idx + strides[mu]];
+      t += lo * xl;
+      t += up * xu;
       k += t;
     }
     G[(int64_t)c * cs + idx] = g[c];
@@ -171,7 +180,8 @@ __device__ __forceinline__ void gf_point_at(const double* __restrict__ u, int64_
   }
 }
 
-// Same, for a flat point index (the batched kernels).
+// Same, for a flat point index (the batched kernels); d in {2, 3} and ncomp
+// in {1, 2} (the batch is checked at creation), uniform over a block.
 template <typename TF>
 __device__ __forceinline__ void gf_point(const double* __restrict__ u, int64_t cs, int64_t idx, int ncomp, int d,
                                          int n1, int n2, int n3, const StencilSet& S, const GParams& gp,
@@ -180,7 +190,13 @@ __device__ __forceinline__ void gf_point(const double* __restrict__ u, int64_t c
   const int64_t r = idx / n1;
   const int i2 = (int)(r % n2);
   const int i3 = (d == 3) ? (int)(r / n2) : 0;
-  gf_point_at<TF>(u, cs, idx, i1, i2, i3, ncomp, d, n1, n2, n3, S, gp, G, F);
+  if (d == 3) {
+    if (ncomp == 2) gf_point_at<TF, 3, 2>(u, cs, idx, i1, i2, i3, n1, n2, n3, S, gp, G, F);
+    else gf_point_at<TF, 3, 1>(u, cs, idx, i1, i2, i3, n1, n2, n3, S, gp, G, F);
+  } else {
+    if (ncomp == 2) gf_point_at<TF, 2, 2>(u, cs, idx, i1, i2, i3, n1, n2, n3, S, gp, G, F);
+    else gf_point_at<TF, 2, 1>(u, cs, idx, i1, i2, i3, n1, n2, n3, S, gp, G, F);
+  }
 }
 
 __device__ __forceinline__ void g_point(const double* __restrict__ u, int64_t cs, int64_t idx, int ncomp,
