@@ -1,7 +1,8 @@
 """GPU parity of the batched integrator (setd_batch_*) against the oracle run
 instance by instance: FP64, 1e-12 relative L2 and inf per field, for every
 tile shape the tuner can pick, ragged and non-square grids, per-instance
-parameters, the dense-K path, d = 3, graph replay, and the 64-instance
+parameters, the dense-K path, d = 3, one component per instance, graph
+replay, and the 64-instance
 workload at full size (sampled instances)."""
 import os
 
@@ -122,6 +123,30 @@ def test_batch_dense_k_path():
     B.step(u, 4, probs[0].g_kind, [p.params for p in probs])
     torch().cuda.synchronize()
     _check(B, u, probs, 4)
+
+
+@pytest.mark.parametrize("dims_list", [[(24, 20), (17, 33), (40, 9)], [(9, 7, 6), (12, 5, 8)]])
+def test_batch_single_component_linear(dims_list):
+    """One component per instance and no reaction: the batched G/F body with a
+    single component, 2D and 3D, ragged sizes.  The oracle's step takes two
+    components, so it runs the field twice (the copy is independent of it)."""
+    tau = 1e-3
+    As = [[[(1.0 + 0.5 * k) * wl.neumann_d2(n) for n in dims]] for k, dims in enumerate(dims_list)]
+    U0s = [wl.random_tensor(dims, 20 + k) for k, dims in enumerate(dims_list)]
+    B = setd.Batch(dims_list, [[[dev(M) for M in Ac] for Ac in A] for A in As], tau)
+    u = torch().zeros(B.total, dtype=torch().float64, device="cuda")
+    for b, U in enumerate(U0s):
+        B.field(u, b, 0).copy_(torch().from_numpy(np.asarray(U).ravel(order="F").copy()))
+    say("single-component batch", dims_list)
+    B.step(u, 4, wl.G_NONE, [])
+    torch().cuda.synchronize()
+    for b, dims in enumerate(dims_list):
+        ref = oracle.integrate([U0s[b], U0s[b]], As[b] + As[b], tau, 4, wl.G_NONE, ())[0]
+        got = B.field(u, b, 0).cpu().numpy().reshape(dims, order="F")
+        e2, ei = rel_l2(got, ref), rel_err(got, ref)
+        say("  inst %d %s rel_l2 %.3e rel_inf %.3e" % (b, dims, e2, ei))
+        assert e2 < TOL and ei < TOL, (b, dims)
+    B.close()
 
 
 def test_batch_three_dimensional():
