@@ -2,8 +2,7 @@
 instance by instance: FP64, 1e-12 relative L2 and inf per field, for every
 tile shape the tuner can pick, ragged and non-square grids, per-instance
 parameters, the dense-K path, d = 3, one component per instance, graph
-replay, and the 64-instance
-workload at full size (sampled instances)."""
+replay, and the 64-instance workload at full size (sampled instances)."""
 import os
 
 import numpy as np
